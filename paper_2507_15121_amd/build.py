@@ -1,0 +1,82 @@
+"""Build the native parts of the package in-tree.
+
+* ``libamped.so``       -- the C-ABI library: host layout builder (g++/OpenMP)
+                           and the gfx950 HIP kernels (hipcc).
+* ``libamped_synth.so`` -- the seeded input generator (gcc/OpenMP), host only.
+
+Every call recompiles.  ``python -m paper_2507_15121_amd.build`` runs it.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+INCLUDE = os.path.join(ROOT, "include")
+BUILD_DIR = os.path.join(HERE, "_build")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = "gfx950"
+
+LIB = os.path.join(HERE, "libamped.so")
+SYNTH_LIB = os.path.join(HERE, "libamped_synth.so")
+
+HIP_SOURCES = ["kernels.hip"]
+HOST_SOURCES = ["api.cpp", "layout.cpp"]
+
+HIPCC_FLAGS = [
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    # CDNA packed-fp32 instructions stay off; plain fp32 code only.
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fp32/fp64 atomic adds as hardware atomics, not CAS loops.
+    "-munsafe-fp-atomics",
+    "-Wall", "-Wno-unused-function",
+]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wextra",
+              "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include")]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build_synth(verbose=False):
+    tmp = SYNTH_LIB + ".tmp"
+    _run(["gcc", "-O3", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+          "-o", tmp, os.path.join(CSRC, "synth.c"), "-lm"], verbose)
+    os.replace(tmp, SYNTH_LIB)
+    return SYNTH_LIB
+
+
+def build_amped(verbose=False, extra_hip_flags=()):
+    hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD_DIR, src + ".o")
+        _run([hipcc] + HIPCC_FLAGS + list(extra_hip_flags) +
+             ["-I" + INCLUDE, "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD_DIR, src + ".o")
+        _run(["g++"] + HOST_FLAGS + ["-I" + INCLUDE, "-I" + CSRC, "-c",
+                                     os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run(["g++", "-shared", "-fopenmp", "-o", tmp] + objs +
+         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-Wl,--no-undefined"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build(verbose=False):
+    build_synth(verbose)
+    build_amped(verbose)
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)
