@@ -1,0 +1,190 @@
+/*
+ * amped.h -- C ABI of the MI355X (gfx950) sparse MTTKRP library.
+ *
+ * The operation is MTTKRP on a sparse tensor along every mode (Eq. 1 in
+ * Sec. 2.1 of Wijeratne, Kannan and Prasanna, "AMPED: Accelerating MTTKRP for
+ * Billion-Scale Sparse Tensor Decomposition on Multiple GPUs", ICPP'25):
+ *
+ *     Y_d[i, r] = sum over nonzeros k with i_d(k) = i of
+ *                 val(k) * prod_{w != d} A_w[i_w(k), r]
+ *
+ * i.e. the elementwise computation ("EC", Sec. 3) summed into a zeroed
+ * output.  Beside it: the same computation with bfloat16 factor matrices and
+ * fp32 accumulation, and the sparse CP least-squares loss over the nonzeros
+ * with its gradient (CP model of Sec. 2.1), whose backward is MTTKRP on the
+ * residuals fused with the residual computation.
+ *
+ * Conventions that hold for every call:
+ *  - Every function returns an amped_status; on a non-OK status nothing was
+ *    enqueued and amped_last_error() returns a message (thread-local, valid
+ *    until the next call on the same thread).  No C++ exception crosses the
+ *    ABI.
+ *  - Index arrays are int32 in the [order][nnz] layout (mode-major, the same
+ *    layout as torch's COO indices), values are fp32.
+ *  - Factor matrices and outputs are caller-owned DEVICE buffers, row-major,
+ *    row stride = rank elements, 16-byte aligned.  They must stay alive until
+ *    the stream's work completes; the library never frees or keeps them.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Launches are asynchronous; device faults surface at the caller's next
+ *    synchronisation.
+ *  - A tensor handle is immutable after creation and binds the HIP device that
+ *    was current at creation.  It owns a small device work queue per mode, so
+ *    calls that use the same handle AND the same mode (or two cp_loss calls)
+ *    must be ordered on one stream; calls on different modes may overlap.
+ *  - Limits: 2 <= order <= 8; 1 <= dims[w] <= 2^31-1; 0 <= nnz <= 2^31-1;
+ *    1 <= rank <= 4096.
+ */
+#ifndef AMPED_H
+#define AMPED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amped_tensor_s *amped_tensor_t;
+
+typedef enum {
+    AMPED_OK = 0,
+    AMPED_ERR_INVALID = 1,     /* null pointer, bad order/mode/rank/size, misalignment   */
+    AMPED_ERR_RANGE = 2,       /* an index outside [0, dims[w]) at creation              */
+    AMPED_ERR_NOMEM = 3,       /* host or device allocation failed, or byte cap exceeded */
+    AMPED_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed             */
+    AMPED_ERR_UNSUPPORTED = 5  /* no usable gfx950 device, or a case not implemented     */
+} amped_status;
+
+/* Creation options; pass NULL for the defaults. */
+typedef struct {
+    int64_t chunk_nnz;        /* CH: nonzeros per work-queue chunk; 0 = 4096.  Part of
+                                 the layout contract (chunk k holds positions
+                                 [k*CH, min((k+1)*CH, nnz)) of a mode's order).        */
+    int64_t device_byte_cap;  /* 0 = no cap; otherwise creation fails with NOMEM,
+                                 before touching the device, if the layouts would
+                                 need more device bytes than this.                     */
+    int32_t keep_perm;        /* 1 = keep each mode's permutation on the device so
+                                 amped_tensor_layout can return it.                    */
+    int32_t reserved;         /* must be 0 */
+} amped_options;
+
+/*
+ * Build the per-mode layouts of a COO tensor and copy them to the current HIP
+ * device.  The paper keeps one copy of the tensor per output mode with all
+ * nonzeros of an output index together (Sec. 3, "Tensor Partitioning"; Sec.
+ * 3.1 tensor sharding) and splits it into equal-size inter-shard partitions
+ * (Sec. 3.1/3.2); here, for every mode d, the nonzeros are put in the order
+ * of the key (i_d, then the other indices in ascending mode order), exact
+ * duplicates keeping their input order, and that order is cut into chunks of
+ * CH nonzeros that the kernels take from a work queue.
+ *
+ *   order    number of modes N (2..8)
+ *   dims     host, [order] mode sizes
+ *   nnz      number of stored entries (duplicates allowed; they add up)
+ *   indices  host, int32 [order][nnz]; need not be sorted
+ *   values   host, fp32 [nnz]
+ *   opts     host, nullable
+ *   out      host, receives the handle (set to NULL on failure)
+ *
+ * The host arrays are only read during the call.  Errors: INVALID for bad
+ * arguments, RANGE for an index outside its mode, NOMEM, HIP, UNSUPPORTED
+ * (no device).
+ */
+amped_status amped_tensor_create(int order, const int64_t *dims, int64_t nnz,
+                                 const int32_t *indices, const float *values,
+                                 const amped_options *opts, amped_tensor_t *out);
+
+/* Synchronise the handle's device, free everything it owns.  NULL is a no-op. */
+amped_status amped_tensor_destroy(amped_tensor_t t);
+
+/*
+ * Shape and layout facts (all outputs host and nullable):
+ *   order; dims[order]; nnz; chunk_nnz (CH); n_chunks = ceil(nnz / CH);
+ *   touched[order] = number of distinct output indices per mode;
+ *   device_bytes = device memory the handle owns.
+ */
+amped_status amped_tensor_info(amped_tensor_t t, int *order, int64_t *dims, int64_t *nnz,
+                               int64_t *chunk_nnz, int64_t *n_chunks, int64_t *touched,
+                               int64_t *device_bytes);
+
+/*
+ * Copy mode `mode`'s device layout back to host arrays (introspection and
+ * tests; synchronous).  All outputs are nullable:
+ *   perm        int32 [nnz]   position -> input nonzero (needs keep_perm=1,
+ *                             else INVALID when requested)
+ *   out_idx     int32 [nnz]   i_mode in layout order (non-decreasing)
+ *   in_idx      int32 [order-1][nnz]  the other indices, modes ascending
+ *   values      fp32  [nnz]
+ *   chunk_flags uint8 [n_chunks]  bit0: chunk's first output index continues
+ *               from the previous chunk; bit1: its last one continues into the
+ *               next chunk.
+ */
+amped_status amped_tensor_layout(amped_tensor_t t, int mode, int32_t *perm, int32_t *out_idx,
+                                 int32_t *in_idx, float *values, uint8_t *chunk_flags);
+
+/*
+ * The same per-mode order and chunk flags, computed on the host only (no
+ * device involved; same builder as amped_tensor_create).  perm: int32 [nnz];
+ * chunk_flags: uint8 [ceil(nnz/chunk_nnz)]; either may be NULL.
+ */
+amped_status amped_layout_host(int order, const int64_t *dims, int64_t nnz,
+                               const int32_t *indices, int mode, int64_t chunk_nnz,
+                               int32_t *perm, uint8_t *chunk_flags);
+
+/*
+ * MTTKRP along `mode` (Eq. 1, Sec. 2.1; one GPU's share of Alg. 1's mode
+ * loop, Sec. 4.6): out[i, r] = sum_{k: i_mode(k)=i} val(k) prod_{w!=mode}
+ * factors[w][i_w(k), r], computed in fp32.
+ *
+ *   factors  host array of `order` DEVICE pointers, factors[w] is dims[w] x rank
+ *            fp32 row-major; factors[mode] is not read (may be NULL)
+ *   out      DEVICE, dims[mode] x rank fp32, fully overwritten (rows with no
+ *            nonzero become 0); must not alias a factor
+ *   stream   hipStream_t or NULL
+ *
+ * Errors (synchronous, nothing enqueued): INVALID for a bad mode/rank, a NULL
+ * or misaligned pointer; HIP if a launch fails.
+ */
+amped_status amped_mttkrp(amped_tensor_t t, int mode, int rank, const float *const *factors,
+                          float *out, void *stream);
+
+/*
+ * MTTKRP with bfloat16 factor matrices: factors[w] holds dims[w] x rank bf16
+ * bit patterns (uint16, row-major, 16-byte aligned).  Each factor value is
+ * widened exactly to fp32; products, accumulation and the fp32 output are as
+ * in amped_mttkrp.  Index arithmetic and segment boundaries are unchanged.
+ */
+amped_status amped_mttkrp_bf16(amped_tensor_t t, int mode, int rank,
+                               const uint16_t *const *factors, float *out, void *stream);
+
+/*
+ * Sparse CP loss at the stored entries (CP model of Sec. 2.1):
+ *   *loss = sum_k (val(k) - sum_r prod_w factors[w][i_w(k), r])^2
+ * Per-entry work in fp32, the sum over entries accumulated in fp64.
+ *   factors  host array of `order` DEVICE fp32 pointers (all read)
+ *   loss     DEVICE, one double, overwritten
+ */
+amped_status amped_cp_loss(amped_tensor_t t, int rank, const float *const *factors,
+                           double *loss, void *stream);
+
+/*
+ * Gradient of the loss above with respect to factors[mode], times -scale/2:
+ *   grad[i, r] = scale * sum_{k: i_mode(k)=i} e(k) prod_{w!=mode} factors[w][i_w(k), r]
+ * with e(k) = val(k) - sum_r prod_w factors[w][i_w(k), r] recomputed on the
+ * fly in the same kernel (nothing per entry is stored).  With
+ * scale = -2 * dL_out the result is dL_out * dLoss/dfactors[mode].
+ *   grad  DEVICE, dims[mode] x rank fp32, fully overwritten; must not alias a factor
+ */
+amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float *const *factors,
+                           float scale, float *grad, void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *amped_last_error(void);
+
+/* Library version string. */
+const char *amped_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMPED_H */

@@ -1,0 +1,475 @@
+// C ABI of the sparse MTTKRP library (declared in include/amped.h): argument
+// checks, handle lifetime, the per-mode layout build (host order, device
+// gather) and the kernel launches.
+#include <hip/hip_runtime_api.h>
+#include <omp.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amped.h"
+#include "internal.h"
+
+using amped::HostModeLayout;
+using amped::kMaxOrder;
+using amped::ModeDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+amped_status fail(amped_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+amped_status hip_fail(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(AMPED_ERR_NOMEM, "%s: out of device memory (%s)", what, hipGetErrorString(e));
+    if (e == hipErrorNotSupported) return fail(AMPED_ERR_UNSUPPORTED, "%s: case not supported", what);
+    return fail(AMPED_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+struct amped_tensor_s {
+    int order = 0;
+    int64_t dims[kMaxOrder] = {};
+    int64_t nnz = 0, chunk = 0, n_chunks = 0;
+    int device = 0;
+    bool keep_perm = false;
+    int64_t device_bytes = 0;
+    std::vector<void*> allocs;
+    ModeDev mode[kMaxOrder];
+    ModeDev loss_dev;                       // mode-0 layout with its own queue
+    int32_t* perm[kMaxOrder] = {};
+    std::vector<uint8_t> flags[kMaxOrder];
+    int64_t touched[kMaxOrder] = {};
+
+    hipError_t alloc(void** p, size_t bytes)
+    {
+        *p = nullptr;
+        if (bytes == 0) return hipSuccess;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) {
+            allocs.push_back(*p);
+            device_bytes += (int64_t)bytes;
+        }
+        return e;
+    }
+    void release(void* p)
+    {
+        for (auto& a : allocs)
+            if (a == p) {
+                (void)hipFree(a);
+                a = nullptr;
+            }
+    }
+    void free_all()
+    {
+        for (void* a : allocs)
+            if (a) (void)hipFree(a);
+        allocs.clear();
+    }
+};
+
+namespace {
+
+amped_status validate_coo(int order, const int64_t* dims, int64_t nnz, const int32_t* indices, const float* values)
+{
+    if (order < 2 || order > kMaxOrder) return fail(AMPED_ERR_INVALID, "order %d outside [2, %d]", order, kMaxOrder);
+    if (!dims) return fail(AMPED_ERR_INVALID, "dims is NULL");
+    for (int w = 0; w < order; ++w)
+        if (dims[w] < 1 || dims[w] > 0x7FFFFFFF)
+            return fail(AMPED_ERR_INVALID, "dims[%d] = %lld outside [1, 2^31-1]", w, (long long)dims[w]);
+    if (nnz < 0 || nnz > 0x7FFFFFFF) return fail(AMPED_ERR_INVALID, "nnz = %lld outside [0, 2^31-1]", (long long)nnz);
+    if (nnz > 0 && (!indices || !values)) return fail(AMPED_ERR_INVALID, "indices or values is NULL");
+    for (int w = 0; w < order; ++w) {
+        const int32_t* col = indices + (int64_t)w * nnz;
+        const int64_t dim = dims[w];
+        int64_t bad = nnz;
+#pragma omp parallel for reduction(min : bad) schedule(static)
+        for (int64_t k = 0; k < nnz; ++k)
+            if (col[k] < 0 || col[k] >= dim) bad = std::min(bad, k);
+        if (bad < nnz)
+            return fail(AMPED_ERR_RANGE, "indices[%d][%lld] = %d outside [0, %lld)", w, (long long)bad, col[bad],
+                        (long long)dim);
+    }
+    return AMPED_OK;
+}
+
+amped_status check_device(int* dev)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(AMPED_ERR_UNSUPPORTED, "no HIP device");
+    if (hipGetDevice(dev) != hipSuccess) return fail(AMPED_ERR_UNSUPPORTED, "no current HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess)
+        return fail(AMPED_ERR_UNSUPPORTED, "cannot query device %d", *dev);
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(AMPED_ERR_UNSUPPORTED, "device %d is %s, this library is built for gfx950", *dev, prop.gcnArchName);
+    return AMPED_OK;
+}
+
+#define HIP_OR_FAIL(call, what)                          \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) {                          \
+            st = hip_fail(e_, what);                     \
+            goto cleanup;                                \
+        }                                                \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* amped_last_error(void) { return g_err.c_str(); }
+
+const char* amped_version(void) { return "amped 0.1.0 (gfx950)"; }
+
+amped_status amped_layout_host(int order, const int64_t* dims, int64_t nnz, const int32_t* indices, int mode,
+                               int64_t chunk_nnz, int32_t* perm, uint8_t* chunk_flags)
+{
+    g_err.clear();
+    static const float dummy = 0.f;
+    amped_status st = validate_coo(order, dims, nnz, indices, nnz ? &dummy : nullptr);
+    if (st != AMPED_OK) return st;
+    if (mode < 0 || mode >= order) return fail(AMPED_ERR_INVALID, "mode %d outside [0, %d)", mode, order);
+    if (chunk_nnz < 1) return fail(AMPED_ERR_INVALID, "chunk_nnz must be >= 1");
+    try {
+        std::vector<int32_t> lex = amped::lex_order(order, dims, nnz, indices);
+        HostModeLayout lay;
+        amped::mode_order(dims, nnz, indices, lex, mode, lay.perm);
+        amped::mode_tables(dims, nnz, indices, mode, chunk_nnz, lay);
+        if (perm && nnz) std::memcpy(perm, lay.perm.data(), (size_t)nnz * sizeof(int32_t));
+        if (chunk_flags && !lay.flags.empty()) std::memcpy(chunk_flags, lay.flags.data(), lay.flags.size());
+    } catch (const std::bad_alloc&) {
+        return fail(AMPED_ERR_NOMEM, "host allocation failed");
+    }
+    return AMPED_OK;
+}
+
+amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, const int32_t* indices,
+                                 const float* values, const amped_options* opts, amped_tensor_t* out)
+{
+    g_err.clear();
+    if (!out) return fail(AMPED_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    amped_status st = validate_coo(order, dims, nnz, indices, values);
+    if (st != AMPED_OK) return st;
+    int64_t chunk = amped::kDefaultChunk, cap = 0;
+    bool keep_perm = false;
+    if (opts) {
+        if (opts->reserved != 0) return fail(AMPED_ERR_INVALID, "options.reserved must be 0");
+        if (opts->chunk_nnz < 0 || opts->chunk_nnz > (1ll << 30))
+            return fail(AMPED_ERR_INVALID, "chunk_nnz %lld outside [0, 2^30]", (long long)opts->chunk_nnz);
+        if (opts->chunk_nnz > 0) chunk = opts->chunk_nnz;
+        if (opts->device_byte_cap < 0) return fail(AMPED_ERR_INVALID, "device_byte_cap < 0");
+        cap = opts->device_byte_cap;
+        if (opts->keep_perm != 0 && opts->keep_perm != 1) return fail(AMPED_ERR_INVALID, "keep_perm must be 0 or 1");
+        keep_perm = opts->keep_perm == 1;
+    }
+    // peak device bytes: the N layouts, the kept permutations, and during the
+    // build the raw COO plus one permutation
+    const int64_t layout_bytes = (int64_t)order * (order + 1) * 4 * nnz;
+    const int64_t peak = layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
+                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8;
+    if (cap > 0 && peak > cap)
+        return fail(AMPED_ERR_NOMEM, "layouts need up to %lld device bytes, cap is %lld", (long long)peak,
+                    (long long)cap);
+    int dev = 0;
+    st = check_device(&dev);
+    if (st != AMPED_OK) return st;
+
+    amped_tensor_s* t = new (std::nothrow) amped_tensor_s();
+    if (!t) return fail(AMPED_ERR_NOMEM, "host allocation failed");
+    t->order = order;
+    for (int w = 0; w < order; ++w) t->dims[w] = dims[w];
+    t->nnz = nnz;
+    t->chunk = chunk;
+    t->n_chunks = (nnz + chunk - 1) / chunk;
+    t->device = dev;
+    t->keep_perm = keep_perm;
+
+    hipStream_t stream = nullptr;
+    void* d_cols[kMaxOrder] = {};
+    void* d_vals = nullptr;
+    void* d_tmp_perm = nullptr;
+    void* d_queues = nullptr;
+    try {
+        std::vector<int32_t> lex = amped::lex_order(order, dims, nnz, indices);
+        HIP_OR_FAIL(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
+        for (int w = 0; w < order; ++w) {
+            HIP_OR_FAIL(t->alloc(&d_cols[w], (size_t)nnz * 4), "hipMalloc(coo)");
+            if (nnz)
+                HIP_OR_FAIL(hipMemcpy(d_cols[w], indices + (int64_t)w * nnz, (size_t)nnz * 4, hipMemcpyHostToDevice),
+                            "hipMemcpy(coo)");
+        }
+        HIP_OR_FAIL(t->alloc(&d_vals, (size_t)nnz * 4), "hipMalloc(values)");
+        if (nnz) HIP_OR_FAIL(hipMemcpy(d_vals, values, (size_t)nnz * 4, hipMemcpyHostToDevice), "hipMemcpy(values)");
+        if (!keep_perm) HIP_OR_FAIL(t->alloc(&d_tmp_perm, (size_t)nnz * 4), "hipMalloc(perm)");
+        HIP_OR_FAIL(t->alloc(&d_queues, (size_t)(order + 1) * sizeof(int)), "hipMalloc(queues)");
+        HIP_OR_FAIL(hipMemset(d_queues, 0, (size_t)(order + 1) * sizeof(int)), "hipMemset(queues)");
+
+        for (int d = 0; d < order; ++d) {
+            HostModeLayout lay;
+            amped::mode_order(dims, nnz, indices, lex, d, lay.perm);
+            amped::mode_tables(dims, nnz, indices, d, chunk, lay);
+            void* d_perm = d_tmp_perm;
+            if (keep_perm) {
+                HIP_OR_FAIL(t->alloc(&d_perm, (size_t)nnz * 4), "hipMalloc(perm)");
+                t->perm[d] = static_cast<int32_t*>(d_perm);
+            }
+            if (nnz)
+                HIP_OR_FAIL(hipMemcpy(d_perm, lay.perm.data(), (size_t)nnz * 4, hipMemcpyHostToDevice),
+                            "hipMemcpy(perm)");
+            ModeDev& m = t->mode[d];
+            void* p = nullptr;
+            HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(out_idx)");
+            HIP_OR_FAIL(amped::launch_permute32(p, d_cols[d], static_cast<int32_t*>(d_perm), nnz, stream), "permute");
+            m.out_idx = static_cast<int32_t*>(p);
+            int j = 0;
+            for (int w = 0; w < order; ++w) {
+                if (w == d) continue;
+                HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(in_idx)");
+                HIP_OR_FAIL(amped::launch_permute32(p, d_cols[w], static_cast<int32_t*>(d_perm), nnz, stream),
+                            "permute");
+                m.in_idx[j++] = static_cast<int32_t*>(p);
+            }
+            HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(values)");
+            HIP_OR_FAIL(amped::launch_permute32(p, d_vals, static_cast<int32_t*>(d_perm), nnz, stream), "permute");
+            m.val = static_cast<float*>(p);
+            if (!lay.split_rows.empty()) {
+                HIP_OR_FAIL(t->alloc(&p, lay.split_rows.size() * 4), "hipMalloc(split)");
+                HIP_OR_FAIL(hipMemcpy(p, lay.split_rows.data(), lay.split_rows.size() * 4, hipMemcpyHostToDevice),
+                            "hipMemcpy(split)");
+                m.split_rows = static_cast<int32_t*>(p);
+            }
+            if (!lay.gaps.empty()) {
+                HIP_OR_FAIL(t->alloc(&p, lay.gaps.size() * 4), "hipMalloc(gaps)");
+                HIP_OR_FAIL(hipMemcpy(p, lay.gaps.data(), lay.gaps.size() * 4, hipMemcpyHostToDevice),
+                            "hipMemcpy(gaps)");
+                m.gaps = static_cast<int32_t*>(p);
+            }
+            m.nnz = nnz;
+            m.chunk = chunk;
+            m.n_chunks = t->n_chunks;
+            m.rows = dims[d];
+            m.n_split = (int64_t)lay.split_rows.size();
+            m.n_gaps = (int64_t)lay.gaps.size() / 2;
+            m.queue = static_cast<int*>(d_queues) + d;
+            t->flags[d] = std::move(lay.flags);
+            t->touched[d] = lay.touched;
+            // the host permutation is reused by the next mode
+            HIP_OR_FAIL(hipStreamSynchronize(stream), "layout build");
+        }
+        t->loss_dev = t->mode[0];
+        t->loss_dev.queue = static_cast<int*>(d_queues) + order;
+    } catch (const std::bad_alloc&) {
+        st = fail(AMPED_ERR_NOMEM, "host allocation failed");
+        goto cleanup;
+    }
+    for (int w = 0; w < order; ++w) {
+        t->device_bytes -= (int64_t)nnz * 4;
+        t->release(d_cols[w]);
+    }
+    t->device_bytes -= (int64_t)nnz * 4;
+    t->release(d_vals);
+    if (d_tmp_perm) {
+        t->device_bytes -= (int64_t)nnz * 4;
+        t->release(d_tmp_perm);
+    }
+    (void)hipStreamDestroy(stream);
+    *out = t;
+    return AMPED_OK;
+
+cleanup:
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+    t->free_all();
+    delete t;
+    return st;
+}
+
+amped_status amped_tensor_destroy(amped_tensor_t t)
+{
+    g_err.clear();
+    if (!t) return AMPED_OK;
+    amped_status st = AMPED_OK;
+    {
+        DeviceGuard guard(t->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
+        t->free_all();
+    }
+    delete t;
+    return st;
+}
+
+amped_status amped_tensor_info(amped_tensor_t t, int* order, int64_t* dims, int64_t* nnz, int64_t* chunk_nnz,
+                               int64_t* n_chunks, int64_t* touched, int64_t* device_bytes)
+{
+    g_err.clear();
+    if (!t) return fail(AMPED_ERR_INVALID, "tensor is NULL");
+    if (order) *order = t->order;
+    if (dims)
+        for (int w = 0; w < t->order; ++w) dims[w] = t->dims[w];
+    if (nnz) *nnz = t->nnz;
+    if (chunk_nnz) *chunk_nnz = t->chunk;
+    if (n_chunks) *n_chunks = t->n_chunks;
+    if (touched)
+        for (int w = 0; w < t->order; ++w) touched[w] = t->touched[w];
+    if (device_bytes) *device_bytes = t->device_bytes;
+    return AMPED_OK;
+}
+
+amped_status amped_tensor_layout(amped_tensor_t t, int mode, int32_t* perm, int32_t* out_idx, int32_t* in_idx,
+                                 float* values, uint8_t* chunk_flags)
+{
+    g_err.clear();
+    if (!t) return fail(AMPED_ERR_INVALID, "tensor is NULL");
+    if (mode < 0 || mode >= t->order) return fail(AMPED_ERR_INVALID, "mode %d outside [0, %d)", mode, t->order);
+    if (perm && !t->keep_perm) return fail(AMPED_ERR_INVALID, "permutation not kept (create with keep_perm=1)");
+    DeviceGuard guard(t->device);
+    if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
+    const ModeDev& m = t->mode[mode];
+    const size_t bytes = (size_t)t->nnz * 4;
+    amped_status st = AMPED_OK;
+    if (bytes) {
+        if (perm) HIP_OR_FAIL(hipMemcpy(perm, t->perm[mode], bytes, hipMemcpyDeviceToHost), "hipMemcpy(perm)");
+        if (out_idx) HIP_OR_FAIL(hipMemcpy(out_idx, m.out_idx, bytes, hipMemcpyDeviceToHost), "hipMemcpy(out_idx)");
+        if (in_idx)
+            for (int j = 0; j < t->order - 1; ++j)
+                HIP_OR_FAIL(hipMemcpy(in_idx + (int64_t)j * t->nnz, m.in_idx[j], bytes, hipMemcpyDeviceToHost),
+                            "hipMemcpy(in_idx)");
+        if (values) HIP_OR_FAIL(hipMemcpy(values, m.val, bytes, hipMemcpyDeviceToHost), "hipMemcpy(values)");
+    }
+    if (chunk_flags && !t->flags[mode].empty()) std::memcpy(chunk_flags, t->flags[mode].data(), t->flags[mode].size());
+    return AMPED_OK;
+cleanup:
+    return st;
+}
+
+namespace {
+
+amped_status check_call(amped_tensor_t t, int mode, int rank, const void* const* factors, const void* out,
+                        bool need_own, const char* out_name)
+{
+    if (!t) return fail(AMPED_ERR_INVALID, "tensor is NULL");
+    if (mode < 0 || mode >= t->order) return fail(AMPED_ERR_INVALID, "mode %d outside [0, %d)", mode, t->order);
+    if (rank < 1 || rank > 4096) return fail(AMPED_ERR_INVALID, "rank %d outside [1, 4096]", rank);
+    if (!factors) return fail(AMPED_ERR_INVALID, "factors is NULL");
+    for (int w = 0; w < t->order; ++w) {
+        if (w == mode && !need_own) continue;
+        if (!factors[w]) return fail(AMPED_ERR_INVALID, "factors[%d] is NULL", w);
+        if (!aligned16(factors[w])) return fail(AMPED_ERR_INVALID, "factors[%d] is not 16-byte aligned", w);
+    }
+    if (!out) return fail(AMPED_ERR_INVALID, "%s is NULL", out_name);
+    if (!aligned16(out)) return fail(AMPED_ERR_INVALID, "%s is not 16-byte aligned", out_name);
+    return AMPED_OK;
+}
+
+amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const* factors, float* out, void* stream,
+                        amped::FactorType ft, amped::Kind kind, float scale)
+{
+    const bool grad = (kind == amped::Kind::ResidualGrad);
+    amped_status st = check_call(t, mode, rank, factors, out, grad, grad ? "grad" : "out");
+    if (st != AMPED_OK) return st;
+    DeviceGuard guard(t->device);
+    if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
+    amped::LaunchArgs a;
+    a.m = &t->mode[mode];
+    a.nin = t->order - 1;
+    a.rank = rank;
+    a.ftype = ft;
+    a.kind = kind;
+    int j = 0;
+    for (int w = 0; w < t->order; ++w)
+        if (w != mode) a.in_factors[j++] = factors[w];
+    a.own_factor = grad ? static_cast<const float*>(factors[mode]) : nullptr;
+    a.scale = scale;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = amped::launch_mttkrp(a);
+    if (e != hipSuccess) return hip_fail(e, grad ? "amped_cp_grad" : "amped_mttkrp");
+    return AMPED_OK;
+}
+
+}  // namespace
+
+amped_status amped_mttkrp(amped_tensor_t t, int mode, int rank, const float* const* factors, float* out,
+                          void* stream)
+{
+    g_err.clear();
+    return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), out, stream,
+                      amped::FactorType::F32, amped::Kind::Mttkrp, 1.0f);
+}
+
+amped_status amped_mttkrp_bf16(amped_tensor_t t, int mode, int rank, const uint16_t* const* factors, float* out,
+                               void* stream)
+{
+    g_err.clear();
+    return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), out, stream,
+                      amped::FactorType::BF16, amped::Kind::Mttkrp, 1.0f);
+}
+
+amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float* const* factors, float scale,
+                           float* grad, void* stream)
+{
+    g_err.clear();
+    return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), grad, stream,
+                      amped::FactorType::F32, amped::Kind::ResidualGrad, scale);
+}
+
+amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* factors, double* loss, void* stream)
+{
+    g_err.clear();
+    amped_status st = check_call(t, 0, rank, reinterpret_cast<const void* const*>(factors), loss, true, "loss");
+    if (st != AMPED_OK) return st;
+    DeviceGuard guard(t->device);
+    if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
+    amped::LossArgs a;
+    a.m = &t->loss_dev;
+    a.order = t->order;
+    a.rank = rank;
+    a.own_factor = factors[0];
+    for (int w = 1; w < t->order; ++w) a.in_factors[w - 1] = factors[w];
+    a.loss = loss;
+    a.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = amped::launch_cp_loss(a);
+    if (e != hipSuccess) return hip_fail(e, "amped_cp_loss");
+    return AMPED_OK;
+}
+
+}  // extern "C"

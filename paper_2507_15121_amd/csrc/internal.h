@@ -1,0 +1,93 @@
+// Internal interfaces shared by the C-ABI layer, the host layout builder and
+// the HIP kernel launchers.  Not installed; not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+namespace amped {
+
+constexpr int kMaxOrder = 8;
+constexpr int64_t kDefaultChunk = 4096;
+// Untouched-row runs shorter than this are zeroed inside the MTTKRP kernel by
+// the wave that reaches them; longer runs go to a list zeroed by the init
+// kernel.  Part of the host/kernel contract.
+constexpr int kGapInKernel = 16;
+
+// ----------------------------------------------------------------- host layout
+struct HostModeLayout {
+    std::vector<int32_t> perm;        // position -> input nonzero
+    std::vector<uint8_t> flags;       // per chunk: bit0 head continues, bit1 tail continues
+    std::vector<int32_t> split_rows;  // output rows shared by two or more chunks
+    std::vector<int32_t> gaps;        // (start, length) pairs of long untouched-row runs
+    int64_t touched = 0;              // distinct output indices
+};
+
+// Position order of the input sorted lexicographically by (i_0, ..., i_{N-1}),
+// stable; an empty vector means the input already is in that order.
+std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, const int32_t* idx);
+
+// Stable order by i_mode of `base` (identity when base is empty).
+void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std::vector<int32_t>& base,
+                int mode, std::vector<int32_t>& perm);
+
+// Chunk flags, split rows, long gaps and touched count of a mode order.
+void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
+                 HostModeLayout& lay);
+
+// Gather idx[w][perm[p]] for p in [p0, p1) into dst.
+void gather_i32(const int32_t* src, const int32_t* perm, int64_t p0, int64_t p1, int32_t* dst);
+void gather_f32(const float* src, const int32_t* perm, int64_t p0, int64_t p1, float* dst);
+
+// -------------------------------------------------------------- device layout
+struct ModeDev {
+    const int32_t* out_idx = nullptr;              // [nnz]
+    const int32_t* in_idx[kMaxOrder - 1] = {};     // other modes ascending, each [nnz]
+    const float* val = nullptr;                    // [nnz]
+    const int32_t* split_rows = nullptr;           // [n_split]
+    const int32_t* gaps = nullptr;                 // [2 * n_gaps]
+    int64_t nnz = 0, chunk = 0, n_chunks = 0, rows = 0, n_split = 0, n_gaps = 0;
+    int* queue = nullptr;                          // device work-queue counter
+};
+
+enum class FactorType { F32 = 0, BF16 = 1 };
+enum class Kind { Mttkrp = 0, ResidualGrad = 1 };
+
+struct LaunchArgs {
+    const ModeDev* m = nullptr;
+    int nin = 0;                                   // number of input modes (order - 1)
+    int rank = 0;
+    FactorType ftype = FactorType::F32;
+    Kind kind = Kind::Mttkrp;
+    const void* in_factors[kMaxOrder - 1] = {};    // input-mode factors, modes ascending
+    const float* own_factor = nullptr;             // factor of the output mode (ResidualGrad)
+    float scale = 1.0f;                            // ResidualGrad output scale
+    float* out = nullptr;
+    hipStream_t stream = nullptr;
+};
+
+// Enqueue init + MTTKRP (or fused residual gradient).  Returns hipSuccess or the
+// launch error.
+hipError_t launch_mttkrp(const LaunchArgs& a);
+
+// Enqueue the CP loss over the given layout (any mode's layout holds every
+// nonzero once).  all_factors are in mode order with the layout's output mode
+// first resolved by the caller: own_factor = factor of the layout's mode.
+struct LossArgs {
+    const ModeDev* m = nullptr;
+    int order = 0;
+    int rank = 0;
+    const float* own_factor = nullptr;
+    const float* in_factors[kMaxOrder - 1] = {};
+    double* loss = nullptr;
+    hipStream_t stream = nullptr;
+};
+hipError_t launch_cp_loss(const LossArgs& a);
+
+// dst[p] = src[perm[p]] for p < n, 32-bit words, on the device.
+hipError_t launch_permute32(void* dst, const void* src, const int32_t* perm, int64_t n, hipStream_t st);
+
+}  // namespace amped

@@ -1,0 +1,202 @@
+// Host side of the per-mode layout builder (preprocessing, Sec. 5.7; not part
+// of the timed MTTKRP).  For every output mode d the nonzeros are ordered by
+// the key (i_d, then the other indices in ascending mode order); exact
+// duplicates keep their input order.  The order is computed with stable
+// parallel LSD radix sorts:
+//   1. if the input is not already lexicographic in (i_0, ..., i_{N-1}), a
+//      lexicographic order is built (LSD over the modes, last mode first);
+//   2. a stable sort of that order by i_d alone then yields the key above,
+//      since among equal i_d the remaining indices stay in lexicographic order.
+// The chunk table follows: chunk k holds positions [k*CH, min((k+1)*CH, nnz)),
+// the fixed-size stand-in for the paper's equal-size inter-shard partitions
+// (Sec. 3.1/3.2).
+#include <omp.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace amped {
+namespace {
+
+int bits_for(uint64_t n)  // bits needed to hold the values 0..n
+{
+    int b = 0;
+    while (b < 64 && (n >> b)) ++b;
+    return b;
+}
+
+// Stable LSD radix sort of (key, val) pairs by key, keys < 2^bits.
+void radix_sort_pairs(std::vector<uint32_t>& keys, std::vector<int32_t>& vals, int bits)
+{
+    const int64_t n = (int64_t)keys.size();
+    if (n <= 1 || bits == 0) return;
+    const int passes = (bits + 11) / 12;
+    const int digit = (bits + passes - 1) / passes;
+    const int nb = 1 << digit;
+    std::vector<uint32_t> k2(n);
+    std::vector<int32_t> v2(n);
+    int nt = omp_get_max_threads();
+    if (nt < 1) nt = 1;
+    if (n < (1 << 16)) nt = 1;
+    std::vector<int64_t> hist((size_t)nt * nb);
+    uint32_t* ks = keys.data();
+    int32_t* vs = vals.data();
+    uint32_t* kd = k2.data();
+    int32_t* vd = v2.data();
+    for (int p = 0; p < passes; ++p) {
+        const int sh = p * digit;
+        const uint32_t mask = (uint32_t)nb - 1;
+        std::fill(hist.begin(), hist.end(), 0);
+#pragma omp parallel num_threads(nt)
+        {
+            const int t = omp_get_thread_num();
+            const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+            int64_t* h = hist.data() + (size_t)t * nb;
+            for (int64_t i = lo; i < hi; ++i) h[(ks[i] >> sh) & mask]++;
+#pragma omp barrier
+#pragma omp single
+            {
+                int64_t run = 0;
+                for (int b = 0; b < nb; ++b)
+                    for (int tt = 0; tt < nt; ++tt) {
+                        const int64_t c = hist[(size_t)tt * nb + b];
+                        hist[(size_t)tt * nb + b] = run;
+                        run += c;
+                    }
+            }
+            for (int64_t i = lo; i < hi; ++i) {
+                const int64_t o = h[(ks[i] >> sh) & mask]++;
+                kd[o] = ks[i];
+                vd[o] = vs[i];
+            }
+        }
+        std::swap(ks, kd);
+        std::swap(vs, vd);
+    }
+    if (ks != keys.data()) {
+        keys.swap(k2);
+        vals.swap(v2);
+    }
+}
+
+// Stable sort of `order` (positions) by idx_w[position].
+void stable_sort_by(const int32_t* idx_w, int64_t dim, std::vector<int32_t>& order)
+{
+    const int64_t n = (int64_t)order.size();
+    std::vector<uint32_t> keys(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) keys[i] = (uint32_t)idx_w[order[i]];
+    radix_sort_pairs(keys, order, bits_for((uint64_t)(dim - 1)));
+}
+
+}  // namespace
+
+std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, const int32_t* idx)
+{
+    int64_t unsorted = 0;
+#pragma omp parallel for reduction(+ : unsorted) schedule(static)
+    for (int64_t k = 1; k < nnz; ++k) {
+        int cmp = 0;
+        for (int w = 0; w < order && cmp == 0; ++w) {
+            const int32_t a = idx[(int64_t)w * nnz + k - 1], b = idx[(int64_t)w * nnz + k];
+            cmp = (a < b) ? -1 : (a > b) ? 1 : 0;
+        }
+        if (cmp > 0) unsorted++;
+    }
+    if (unsorted == 0) return {};
+    std::vector<int32_t> perm(nnz);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nnz; ++k) perm[k] = (int32_t)k;
+    for (int w = order - 1; w >= 0; --w) stable_sort_by(idx + (int64_t)w * nnz, dims[w], perm);
+    return perm;
+}
+
+void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std::vector<int32_t>& base,
+                int mode, std::vector<int32_t>& perm)
+{
+    perm.resize(nnz);
+    if (base.empty()) {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nnz; ++k) perm[k] = (int32_t)k;
+    } else {
+        std::memcpy(perm.data(), base.data(), (size_t)nnz * sizeof(int32_t));
+    }
+    if (mode == 0 && base.empty()) return;  // lexicographic input is already in mode-0 order
+    stable_sort_by(idx + (int64_t)mode * nnz, dims[mode], perm);
+}
+
+void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
+                 HostModeLayout& lay)
+{
+    const int32_t* col = idx + (int64_t)mode * nnz;
+    const int32_t* perm = lay.perm.data();
+    auto key = [&](int64_t p) { return col[perm[p]]; };
+    const int64_t n_chunks = (nnz + chunk - 1) / chunk;
+    lay.flags.assign(n_chunks, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n_chunks; ++k) {
+        const int64_t s = k * chunk, e = std::min(s + chunk, nnz);
+        uint8_t f = 0;
+        if (k > 0 && key(s - 1) == key(s)) f |= 1;
+        if (e < nnz && key(e - 1) == key(e)) f |= 2;
+        lay.flags[k] = f;
+    }
+    lay.split_rows.clear();
+    for (int64_t k = 1; k < n_chunks; ++k)
+        if (lay.flags[k] & 1) {
+            const int32_t r = key(k * chunk);
+            if (lay.split_rows.empty() || lay.split_rows.back() != r) lay.split_rows.push_back(r);
+        }
+    // distinct output indices and long runs of untouched rows
+    int nt = omp_get_max_threads();
+    if (nt < 1) nt = 1;
+    std::vector<std::vector<int32_t>> tgaps(nt);
+    int64_t touched = 0;
+#pragma omp parallel num_threads(nt) reduction(+ : touched)
+    {
+        const int t = omp_get_thread_num();
+        const int64_t lo = nnz * t / nt, hi = nnz * (t + 1) / nt;
+        for (int64_t p = lo; p < hi; ++p) {
+            const int64_t cur = key(p);
+            const int64_t prev = (p == 0) ? -1 : key(p - 1);
+            if (cur != prev) {
+                touched++;
+                if (cur - prev - 1 >= kGapInKernel) {
+                    tgaps[t].push_back((int32_t)(prev + 1));
+                    tgaps[t].push_back((int32_t)(cur - prev - 1));
+                }
+            }
+        }
+    }
+    lay.touched = touched;
+    lay.gaps.clear();
+    for (int t = 0; t < nt; ++t) lay.gaps.insert(lay.gaps.end(), tgaps[t].begin(), tgaps[t].end());
+    const int64_t rows = dims[mode];
+    if (nnz == 0) {
+        lay.gaps.push_back(0);
+        lay.gaps.push_back((int32_t)rows);
+    } else {
+        const int64_t last = key(nnz - 1);
+        if (rows - last - 1 >= kGapInKernel) {
+            lay.gaps.push_back((int32_t)(last + 1));
+            lay.gaps.push_back((int32_t)(rows - last - 1));
+        }
+    }
+}
+
+void gather_i32(const int32_t* src, const int32_t* perm, int64_t p0, int64_t p1, int32_t* dst)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t p = p0; p < p1; ++p) dst[p - p0] = src[perm[p]];
+}
+
+void gather_f32(const float* src, const int32_t* perm, int64_t p0, int64_t p1, float* dst)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t p = p0; p < p1; ++p) dst[p - p0] = src[perm[p]];
+}
+
+}  // namespace amped
