@@ -1,0 +1,260 @@
+"""All-mode sparse MTTKRP benchmark on one MI355X.
+
+One step = MTTKRP along every mode of the tensor (each mode into its own
+output, all from the same factors), the paper's metric "time to compute
+MTTKRP across all modes in one iteration" (Sec. 5.1).  Inputs are resident in
+HBM before the timed region; the layout build is excluded (as preprocessing is
+in the paper).  Printed as one JSON line; beside the fp32 value it reports the
+bf16-factor form, the sparse CP loss forward + fused backward, the dominant
+kernel's roofline figures and the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MTTKRP nnz/s + achieved HBM TB/s per mode; FP32 vs BF16-factor at stated tol"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="zipf3-10Mx5Mx2M-200M")
+    ap.add_argument("--nnz", type=int, default=None, help="override the workload's nonzero count")
+    ap.add_argument("--rank", type=int, default=None, help="override the workload's rank")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and CP loss/grad forms")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter scaling)")
+    return ap.parse_args()
+
+
+def sampled_rel_errors(st, factors64, outs, rank, rng, n_rows=200):
+    """Relative Frobenius error of each mode's output on sampled rows (the
+    heaviest row plus random touched rows) against the FP64 oracle."""
+    import oracle
+    errs = []
+    for d, out in enumerate(outs):
+        col = st.idx[d]
+        counts = np.bincount(col, minlength=st.dims[d])
+        touched = np.flatnonzero(counts)
+        pick = rng.choice(touched, size=min(n_rows, touched.size), replace=False)
+        rows = np.unique(np.concatenate([pick, [int(np.argmax(counts))]]))
+        lut = np.full(st.dims[d], -1, dtype=np.int64)
+        lut[rows] = np.arange(rows.size)
+        m = lut[col] >= 0
+        sub = st.idx[:, m].copy()
+        sub[d] = lut[sub[d]]
+        dims = list(st.dims)
+        dims[d] = rows.size
+        fs = list(factors64)
+        fs[d] = np.zeros((rows.size, rank))
+        ref = oracle.mttkrp(sub, st.val[m], dims, fs, d)
+        errs.append(oracle.rel_fro(out[rows], ref))
+    return errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2507_15121_amd import api, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    wl = synth.WORKLOADS[args.workload]
+    seed = synth.DEFAULT_SEED if args.seed is None else args.seed
+    R = args.rank or wl.rank
+    nnz = wl.nnz if args.nnz is None else args.nnz
+
+    t0 = time.time()
+    st = synth.workload(wl.name, seed=seed, nnz=nnz)
+    factors = synth.factors(st.dims, R, seed=seed)
+    gen_s = time.time() - t0
+    log("generated %s nnz=%d in %.1fs (%s)" % (wl.name, st.nnz, gen_s, st.info))
+
+    t0 = time.time()
+    T = api.Tensor(st.idx, st.val, st.dims, chunk_nnz=args.chunk)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log("layouts built in %.1fs, device bytes %.2f GB, touched %s" % (build_s, T.device_bytes / 1e9, T.touched))
+
+    N = st.order
+    dfac = [torch.from_numpy(f).cuda() for f in factors]
+    outs = [torch.empty((st.dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
+    stream = torch.cuda.current_stream()
+
+    def step(fac, bf16=False, ev=None):
+        for d in range(N):
+            f = [None if w == d else x for w, x in enumerate(fac)]
+            if ev is not None:
+                ev[d][0].record(stream)
+            if bf16:
+                api.mttkrp_bf16(T, d, f, out=outs[d], stream=stream)
+            else:
+                api.mttkrp(T, d, f, out=outs[d], stream=stream)
+            if ev is not None:
+                ev[d][1].record(stream)
+
+    def timed(fac, bf16=False):
+        for _ in range(args.warmup):
+            step(fac, bf16)
+        torch.cuda.synchronize()
+        evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(N)]
+               for _ in range(args.steps)]
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        start.record(stream)
+        for k in range(args.steps):
+            step(fac, bf16, evs[k])
+        end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        per_mode = [float(np.mean([evs[k][d][0].elapsed_time(evs[k][d][1]) for k in range(args.steps)]))
+                    for d in range(N)]
+        return start.elapsed_time(end) / args.steps, per_mode, wall
+
+    ms_step, per_mode_ms, wall = timed(dfac)
+    log("fp32: %.3f ms/step, per mode %s ms, wall %.3fs" % (ms_step, ["%.3f" % x for x in per_mode_ms], wall))
+
+    # algorithmic bytes per mode: nonzero stream + each distinct input row once + output once
+    def mode_bytes(d, fbytes):
+        stream_b = st.nnz * (4 * N + 4)
+        gather_b = sum(T.touched[w] * R * fbytes for w in range(N) if w != d)
+        out_b = st.dims[d] * R * 4
+        return stream_b + gather_b + out_b
+    bytes32 = [mode_bytes(d, 4) for d in range(N)]
+    achieved = sum(bytes32) / (sum(per_mode_ms) * 1e-3) / 1e9
+    per_mode = [{"mode": d, "rows": st.dims[d], "touched": T.touched[d], "ms": per_mode_ms[d],
+                 "nnz_per_s": st.nnz / (per_mode_ms[d] * 1e-3),
+                 "algorithmic_GBps": bytes32[d] / (per_mode_ms[d] * 1e-3) / 1e9} for d in range(N)]
+
+    rng = np.random.default_rng(7)
+    factors64 = None
+    acc = {}
+    if not args.no_accuracy:
+        factors64 = [f.astype(np.float64) for f in factors]
+        step(dfac)
+        torch.cuda.synchronize()
+        host_outs = [o.cpu().numpy() for o in outs]
+        acc["fp32_rel_err_sampled"] = sampled_rel_errors(st, factors64, host_outs, R, rng)
+        log("fp32 sampled rel errors %s" % acc["fp32_rel_err_sampled"])
+
+    forms = {}
+    if not args.no_forms:
+        dbf = [f.to(torch.bfloat16) for f in dfac]
+        ms_bf, pm_bf, _ = timed(dbf, bf16=True)
+        bytes16 = [mode_bytes(d, 2) for d in range(N)]
+        forms["bf16"] = {"ms_per_step": ms_bf, "per_mode_ms": pm_bf,
+                         "nnz_per_s": N * st.nnz / (ms_bf * 1e-3),
+                         "algorithmic_GBps": sum(bytes16) / (sum(pm_bf) * 1e-3) / 1e9}
+        if not args.no_accuracy:
+            step(dbf, bf16=True)
+            torch.cuda.synchronize()
+            host_outs = [o.cpu().numpy() for o in outs]
+            forms["bf16"]["rel_err_vs_fp64_sampled"] = sampled_rel_errors(st, factors64, host_outs, R, rng)
+        log("bf16: %s" % forms["bf16"])
+        # sparse CP loss forward + fused residual/MTTKRP backward for every mode
+        grads = [torch.empty_like(f) for f in dfac]
+        loss = torch.empty((), dtype=torch.float64, device="cuda")
+
+        def cp_step():
+            api.cp_loss(T, dfac, out=loss, stream=stream)
+            for d in range(N):
+                api.cp_grad(T, d, dfac, -2.0, out=grads[d], stream=stream)
+        for _ in range(args.warmup):
+            cp_step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            cp_step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_cp = a.elapsed_time(b) / args.steps
+        forms["cp_loss_and_grad"] = {"ms_per_step": ms_cp, "loss": float(loss),
+                                     "nnz_per_s": (N + 1) * st.nnz / (ms_cp * 1e-3)}
+        log("cp loss+grad: %s" % forms["cp_loss_and_grad"])
+
+    if args.copy_calibration:
+        n = 1 << 30  # 4 GiB of fp32 read, 4 GiB written
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        if factors64 is None:
+            factors64 = [f.astype(np.float64) for f in factors]
+        val64 = st.val.astype(np.float64)
+        crng = np.random.default_rng(11)
+
+        def run_sample(S):
+            sel = np.sort(crng.choice(st.nnz, size=S, replace=False))
+            sub, sv = np.ascontiguousarray(st.idx[:, sel]), val64[sel]
+            c0 = time.perf_counter()
+            for d in range(N):
+                oracle.mttkrp(sub, sv, st.dims, factors64, d)
+            return time.perf_counter() - c0
+        S0 = min(st.nnz, 200_000)
+        t_probe = run_sample(S0)
+        S = int(min(st.nnz, max(S0, S0 * args.cpu_seconds / max(t_probe, 1e-6))))
+        t_cpu = run_sample(S) if S > S0 else t_probe
+        cpu = {"value": N * S / t_cpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+               "sample": "%d random nonzeros of the same tensor, all %d modes, full-size factors and "
+                         "outputs, float64, one thread; %.1fs" % (S, N, t_cpu)}
+        log("cpu baseline %s" % cpu)
+
+    value = N * st.nnz / (ms_step * 1e-3)
+    res = {
+        "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "dims": list(st.dims), "nnz": st.nnz, "rank": R,
+                   "dist": wl.dist, "zipf_s": wl.zipf_s, "hot_frac": wl.hot_frac,
+                   "chunk_nnz": T.chunk_nnz, "seed": seed,
+                   "value_is": "modes x nnz / all-mode step time"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "mttkrp_kernel (fp32)",
+                     "bytes_model": "per mode: nnz*(4N+4) + sum_{w!=d} touched_w*R*4 + I_d*R*4"},
+        "per_mode": per_mode,
+        "forms": forms,
+        "accuracy": acc,
+        "layout_build_s": build_s, "generate_s": gen_s,
+        "cpu_baseline": cpu,
+    }
+    T.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,7 +12,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libamped.so")
+# AMPED_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("AMPED_LIB") or os.path.join(_HERE, "libamped.so")
 
 OK, ERR_INVALID, ERR_RANGE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "RANGE", 3: "NOMEM", 4: "HIP", 5: "UNSUPPORTED"}

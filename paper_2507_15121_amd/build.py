@@ -51,26 +51,29 @@ def build_synth(verbose=False):
     return SYNTH_LIB
 
 
-def build_amped(verbose=False, extra_hip_flags=()):
+def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None):
+    """Build libamped.so (or, with `out`, a variant with extra hipcc flags)."""
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    lib_path = out or LIB
+    bdir = build_dir or BUILD_DIR
+    os.makedirs(bdir, exist_ok=True)
     objs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD_DIR, src + ".o")
+        obj = os.path.join(bdir, src + ".o")
         _run([hipcc] + HIPCC_FLAGS + list(extra_hip_flags) +
              ["-I" + INCLUDE, "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD_DIR, src + ".o")
+        obj = os.path.join(bdir, src + ".o")
         _run(["g++"] + HOST_FLAGS + ["-I" + INCLUDE, "-I" + CSRC, "-c",
                                      os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     _run(["g++", "-shared", "-fopenmp", "-o", tmp] + objs +
          ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
           "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-Wl,--no-undefined"], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 def build(verbose=False):

@@ -116,14 +116,17 @@ __device__ __forceinline__ float group_sum(float x)
 }
 
 // ------------------------------------------------------------------ row access
-// Row<T, RPL>: RPL consecutive columns of a factor row as fp32.
+// Row<T, RPL>: RPL consecutive columns of a factor row as fp32.  `lp` is the
+// lane's base pointer (factor + its first column), `rb` the row stride in
+// bytes (a compile-time constant on the vector path, so the address is one
+// 64-bit shift-add).
 template <typename T, int RPL> struct Row;
 
 template <> struct Row<float, 4> {
     using Raw = float4;
-    static __device__ __forceinline__ Raw load(const void* base, int64_t row, int64_t ld, int c)
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
     {
-        return *reinterpret_cast<const float4*>(static_cast<const float*>(base) + row * ld + c);
+        return *reinterpret_cast<const float4*>(lp + (uint64_t)row * rb);
     }
     static __device__ __forceinline__ Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
@@ -134,9 +137,9 @@ template <> struct Row<float, 4> {
 
 template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
     using Raw = uint4;
-    static __device__ __forceinline__ Raw load(const void* base, int64_t row, int64_t ld, int c)
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
     {
-        return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + row * ld + c);
+        return *reinterpret_cast<const uint4*>(lp + (uint64_t)row * rb);
     }
     static __device__ __forceinline__ Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[8])
@@ -152,9 +155,9 @@ template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
 
 template <> struct Row<float, 1> {
     using Raw = float;
-    static __device__ __forceinline__ Raw load(const void* base, int64_t row, int64_t ld, int c)
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
     {
-        return static_cast<const float*>(base)[row * ld + c];
+        return *reinterpret_cast<const float*>(lp + (uint64_t)row * rb);
     }
     static __device__ __forceinline__ Raw zero() { return 0.f; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = r; }
@@ -162,9 +165,9 @@ template <> struct Row<float, 1> {
 
 template <> struct Row<uint16_t, 1> {
     using Raw = uint32_t;
-    static __device__ __forceinline__ Raw load(const void* base, int64_t row, int64_t ld, int c)
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
     {
-        return static_cast<const uint16_t*>(base)[row * ld + c];
+        return *reinterpret_cast<const uint16_t*>(lp + (uint64_t)row * rb);
     }
     static __device__ __forceinline__ Raw zero() { return 0u; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = __uint_as_float(r << 16); }
@@ -252,8 +255,10 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
     constexpr int G = 64 / LPR;                       // nonzero groups per wave
     constexpr int RT = LPR * RPL;                     // columns per wave row
     constexpr int UMAX = (NIN <= 2) ? 8 : 4;
-    constexpr int U = (LPR < UMAX) ? LPR : UMAX;      // sub-steps per gather batch
-    constexpr int NB = LPR / U;
+    constexpr int MPL = (LPR < UMAX) ? UMAX / LPR : 1;  // nonzeros of metadata per lane
+    constexpr int TS = LPR * MPL;                     // nonzeros per group per tile
+    constexpr int U = (TS < UMAX) ? TS : UMAX;        // sub-steps per gather batch
+    constexpr int NB = TS / U;                        // batches per tile (MPL == 1 if NB > 1)
     using RowT = Row<T, RPL>;
     using OwnRow = Row<float, (KIND == 1) ? RPL : 1>;
     static_assert(KIND == 0 || std::is_same<T, float>::value, "residual form is fp32 only");
@@ -262,21 +267,29 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
     __shared__ int s_ext[kWaves][2 * G];
     __shared__ float s_acc[kWaves][2 * G][RT];
 
+    // vector path: the row is exactly RT columns, so the strides are constants
+    constexpr bool VEC = RPL > 1;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int g = lane / LPR;
     const int s = lane % LPR;
-    const int c = p.col0 + s * RPL;                   // this lane's first column
-    const bool lane_on = s * RPL < p.ncols;
-    const int64_t ld = p.ld;
+    const bool lane_on = VEC || (s * RPL < p.ncols);
+    const int c = p.col0 + (lane_on ? s * RPL : 0);   // this lane's first column (kept in the row)
+    const int64_t ld = VEC ? (int64_t)RT : p.ld;
+    const uint64_t rb = (uint64_t)ld * sizeof(T);
+    const uint64_t rb_own = (uint64_t)ld * sizeof(float);
     const float oscale = (KIND == 1) ? p.scale : 1.0f;
+    const char* lbase[NIN];
+#pragma unroll
+    for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(T);
+    const char* obase = (KIND == 1) ? reinterpret_cast<const char*>(p.own + c) : nullptr;
 
     for (;;) {
         const int chunk = pop_chunk(p.queue, lane);
         if (chunk >= p.n_chunks) break;
         const int64_t cs = (int64_t)chunk * p.chunk;
         const int64_t ce = min(cs + p.chunk, p.nnz);
-        const int64_t Lg = ((ce - cs + G * LPR - 1) / (G * LPR)) * LPR;
+        const int64_t Lg = ((ce - cs + G * TS - 1) / (G * TS)) * TS;
         const int64_t gs = cs + g * Lg;
         const int64_t ge = min(gs + Lg, ce);
         const bool gon = gs < ge;
@@ -322,21 +335,33 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
             }
         };
 
-        const int64_t ntiles = Lg / LPR;
-        for (int64_t t = 0; t < ntiles; ++t) {
-            const int64_t base = gs + t * LPR;
-            const int64_t mp = base + s;
-            int m_key = 0;
-            int m_idx[NIN];
-            float m_val = 0.f;
+        // lane s of a group holds the metadata of nonzero gs + t*LPR + s; the
+        // next tile's metadata is loaded while this tile's rows are in flight
+        const int ntiles = (int)(Lg / TS);
+        // lane s holds nonzeros base + m*LPR + s, m < MPL
+        int m_key[MPL], m_idx[MPL][NIN];
+        float m_val[MPL];
+        auto load_meta = [&](int t, int (&key)[MPL], int (&ix)[MPL][NIN], float (&v)[MPL]) {
 #pragma unroll
-            for (int w = 0; w < NIN; ++w) m_idx[w] = 0;
-            if (gon && mp < ge) {
-                m_key = __builtin_nontemporal_load(p.out_idx + mp);
+            for (int m = 0; m < MPL; ++m) {
+                key[m] = 0;
+                v[m] = 0.f;
 #pragma unroll
-                for (int w = 0; w < NIN; ++w) m_idx[w] = __builtin_nontemporal_load(p.in_idx[w] + mp);
-                m_val = __builtin_nontemporal_load(p.val + mp);
+                for (int w = 0; w < NIN; ++w) ix[m][w] = 0;
+                const int64_t mp = gs + (int64_t)t * TS + m * LPR + s;
+                if (gon && t < ntiles && mp < ge) {
+                    key[m] = __builtin_nontemporal_load(p.out_idx + mp);
+#pragma unroll
+                    for (int w = 0; w < NIN; ++w) ix[m][w] = __builtin_nontemporal_load(p.in_idx[w] + mp);
+                    v[m] = __builtin_nontemporal_load(p.val + mp);
+                }
             }
+        };
+        load_meta(0, m_key, m_idx, m_val);
+        for (int t = 0; t < ntiles; ++t) {
+            const int64_t base = gs + (int64_t)t * TS;
+            int n_key[MPL], n_idx[MPL][NIN];
+            float n_val[MPL];
 #pragma unroll 1
             for (int jb = 0; jb < NB; ++jb) {
                 typename RowT::Raw raw[U][NIN];
@@ -344,19 +369,26 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
                 int keys[U];
                 float vals[U];
                 bool valid[U];
+                // issue every gather of the batch first (idle slots read row 0)
                 static_for<U>([&](auto ju) {
                     constexpr int JU = decltype(ju)::value;
+                    constexpr int M = (NB == 1) ? JU / LPR : 0;   // which of the lane's nonzeros
+                    constexpr int JL = (NB == 1) ? JU % LPR : JU; // which lane of the group
                     valid[ju] = gon && (base + jb * U + JU < ge);
-                    keys[ju] = tile_bcast<LPR, U, NB, JU>(m_key, jb, lane);
-                    vals[ju] = tile_bcast_f<LPR, U, NB, JU>(m_val, jb, lane);
+                    keys[ju] = tile_bcast<LPR, U, NB, JL>(m_key[M], jb, lane);
+                    vals[ju] = tile_bcast_f<LPR, U, NB, JL>(m_val[M], jb, lane);
 #pragma unroll
                     for (int w = 0; w < NIN; ++w) {
-                        const int ix = tile_bcast<LPR, U, NB, JU>(m_idx[w], jb, lane);
-                        raw[ju][w] = (valid[ju] && lane_on) ? RowT::load(p.fac[w], ix, ld, c) : RowT::zero();
+                        const int ix = tile_bcast<LPR, U, NB, JL>(m_idx[M][w], jb, lane);
+                        if constexpr (VEC) raw[ju][w] = RowT::load(lbase[w], ix, rb);
+                        else raw[ju][w] = lane_on ? RowT::load(lbase[w], ix, rb) : RowT::zero();
                     }
-                    if constexpr (KIND == 1)
-                        own[ju] = (valid[ju] && lane_on) ? OwnRow::load(p.own, keys[ju], ld, c) : OwnRow::zero();
+                    if constexpr (KIND == 1) {
+                        if constexpr (VEC) own[ju] = OwnRow::load(obase, keys[ju], rb_own);
+                        else own[ju] = lane_on ? OwnRow::load(obase, keys[ju], rb_own) : OwnRow::zero();
+                    }
                 });
+                if (jb == 0) load_meta(t + 1, n_key, n_idx, n_val);
                 static_for<U>([&](auto ju) {
                     float prod[RPL];
                     {
@@ -396,6 +428,13 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
                         for (int i = 0; i < RPL; ++i) acc[i] = fmaf(coef, prod[i], acc[i]);
                     }
                 });
+            }
+#pragma unroll
+            for (int m = 0; m < MPL; ++m) {
+                m_key[m] = n_key[m];
+                m_val[m] = n_val[m];
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) m_idx[m][w] = n_idx[m][w];
             }
         }
 
@@ -463,23 +502,32 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
 }
 
 // ------------------------------------------------------------------ CP loss
-// Sum over nonzeros of (val - sum_r prod_w A_w[i_w, r])^2; one lane per group
-// accumulates its squared residuals in fp64; one fp64 atomic per wave.
+// Sum over nonzeros of (val - sum_r prod_w A_w[i_w, r])^2: per-entry work in
+// fp32, each squared residual added in fp64 by the group's first lane, one
+// fp64 atomic per wave.
 template <int NIN, int LPR, int RPL>
 __global__ void __launch_bounds__(kBlock) cp_loss_kernel(const KParams p)
 {
     constexpr int G = 64 / LPR;
+    constexpr int RT = LPR * RPL;
     constexpr int UMAX = (NIN <= 2) ? 8 : 4;
-    constexpr int U = (LPR < UMAX) ? LPR : UMAX;
-    constexpr int NB = LPR / U;
+    constexpr int MPL = (LPR < UMAX) ? UMAX / LPR : 1;  // nonzeros of metadata per lane
+    constexpr int TS = LPR * MPL;                     // nonzeros per group per tile
+    constexpr int U = (TS < UMAX) ? TS : UMAX;        // sub-steps per gather batch
+    constexpr int NB = TS / U;                        // batches per tile (MPL == 1 if NB > 1)
+    constexpr bool VEC = RPL > 1;
     using RowT = Row<float, RPL>;
 
     const int lane = threadIdx.x & 63;
     const int g = lane / LPR;
     const int s = lane % LPR;
-    const int c = p.col0 + s * RPL;
-    const bool lane_on = s * RPL < p.ncols;
-    const int64_t ld = p.ld;
+    const bool lane_on = VEC || (s * RPL < p.ncols);
+    const int c = p.col0 + (lane_on ? s * RPL : 0);
+    const uint64_t rb = (uint64_t)(VEC ? (int64_t)RT : p.ld) * sizeof(float);
+    const char* lbase[NIN + 1];
+#pragma unroll
+    for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(float);
+    lbase[NIN] = reinterpret_cast<const char*>(p.own + c);
     double lsum = 0.0;
 
     for (;;) {
@@ -487,26 +535,35 @@ __global__ void __launch_bounds__(kBlock) cp_loss_kernel(const KParams p)
         if (chunk >= p.n_chunks) break;
         const int64_t cs = (int64_t)chunk * p.chunk;
         const int64_t ce = min(cs + p.chunk, p.nnz);
-        const int64_t Lg = ((ce - cs + G * LPR - 1) / (G * LPR)) * LPR;
+        const int64_t Lg = ((ce - cs + G * TS - 1) / (G * TS)) * TS;
         const int64_t gs = cs + g * Lg;
         const int64_t ge = min(gs + Lg, ce);
         const bool gon = gs < ge;
-        const int64_t ntiles = Lg / LPR;
-        float csum = 0.f;  // this chunk's squared residuals of the group (fp32, <= CH/G terms)
-        for (int64_t t = 0; t < ntiles; ++t) {
-            const int64_t base = gs + t * LPR;
-            const int64_t mp = base + s;
-            int m_key = 0;
-            int m_idx[NIN];
-            float m_val = 0.f;
+        const int ntiles = (int)(Lg / TS);
+        // lane s holds nonzeros base + m*LPR + s, m < MPL
+        int m_key[MPL], m_idx[MPL][NIN];
+        float m_val[MPL];
+        auto load_meta = [&](int t, int (&key)[MPL], int (&ix)[MPL][NIN], float (&v)[MPL]) {
 #pragma unroll
-            for (int w = 0; w < NIN; ++w) m_idx[w] = 0;
-            if (gon && mp < ge) {
-                m_key = __builtin_nontemporal_load(p.out_idx + mp);
+            for (int m = 0; m < MPL; ++m) {
+                key[m] = 0;
+                v[m] = 0.f;
 #pragma unroll
-                for (int w = 0; w < NIN; ++w) m_idx[w] = __builtin_nontemporal_load(p.in_idx[w] + mp);
-                m_val = __builtin_nontemporal_load(p.val + mp);
+                for (int w = 0; w < NIN; ++w) ix[m][w] = 0;
+                const int64_t mp = gs + (int64_t)t * TS + m * LPR + s;
+                if (gon && t < ntiles && mp < ge) {
+                    key[m] = __builtin_nontemporal_load(p.out_idx + mp);
+#pragma unroll
+                    for (int w = 0; w < NIN; ++w) ix[m][w] = __builtin_nontemporal_load(p.in_idx[w] + mp);
+                    v[m] = __builtin_nontemporal_load(p.val + mp);
+                }
             }
+        };
+        load_meta(0, m_key, m_idx, m_val);
+        for (int t = 0; t < ntiles; ++t) {
+            const int64_t base = gs + (int64_t)t * TS;
+            int n_key[MPL], n_idx[MPL][NIN];
+            float n_val[MPL];
 #pragma unroll 1
             for (int jb = 0; jb < NB; ++jb) {
                 typename RowT::Raw raw[U][NIN + 1];
@@ -514,16 +571,21 @@ __global__ void __launch_bounds__(kBlock) cp_loss_kernel(const KParams p)
                 bool valid[U];
                 static_for<U>([&](auto ju) {
                     constexpr int JU = decltype(ju)::value;
+                    constexpr int M = (NB == 1) ? JU / LPR : 0;
+                    constexpr int JL = (NB == 1) ? JU % LPR : JU;
                     valid[ju] = gon && (base + jb * U + JU < ge);
-                    vals[ju] = tile_bcast_f<LPR, U, NB, JU>(m_val, jb, lane);
-                    const int kk = tile_bcast<LPR, U, NB, JU>(m_key, jb, lane);
-                    raw[ju][NIN] = (valid[ju] && lane_on) ? RowT::load(p.own, kk, ld, c) : RowT::zero();
+                    vals[ju] = tile_bcast_f<LPR, U, NB, JL>(m_val[M], jb, lane);
+                    const int kk = tile_bcast<LPR, U, NB, JL>(m_key[M], jb, lane);
+                    if constexpr (VEC) raw[ju][NIN] = RowT::load(lbase[NIN], kk, rb);
+                    else raw[ju][NIN] = lane_on ? RowT::load(lbase[NIN], kk, rb) : RowT::zero();
 #pragma unroll
                     for (int w = 0; w < NIN; ++w) {
-                        const int ix = tile_bcast<LPR, U, NB, JU>(m_idx[w], jb, lane);
-                        raw[ju][w] = (valid[ju] && lane_on) ? RowT::load(p.fac[w], ix, ld, c) : RowT::zero();
+                        const int ix = tile_bcast<LPR, U, NB, JL>(m_idx[M][w], jb, lane);
+                        if constexpr (VEC) raw[ju][w] = RowT::load(lbase[w], ix, rb);
+                        else raw[ju][w] = lane_on ? RowT::load(lbase[w], ix, rb) : RowT::zero();
                     }
                 });
+                if (jb == 0) load_meta(t + 1, n_key, n_idx, n_val);
                 static_for<U>([&](auto ju) {
                     float prod[RPL];
                     RowT::unpack(raw[ju][NIN], prod);
@@ -538,11 +600,17 @@ __global__ void __launch_bounds__(kBlock) cp_loss_kernel(const KParams p)
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) part += prod[i];
                     const float e = vals[ju] - group_sum<LPR>(part);
-                    if (valid[ju]) csum = fmaf(e, e, csum);
+                    if (valid[ju] && s == 0) lsum = fma((double)e, (double)e, lsum);
                 });
             }
+#pragma unroll
+            for (int m = 0; m < MPL; ++m) {
+                m_key[m] = n_key[m];
+                m_val[m] = n_val[m];
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) m_idx[m][w] = n_idx[m][w];
+            }
         }
-        if (s == 0) lsum += (double)csum;
     }
     // wave sum in fp64, one atomic per wave
 #pragma unroll

@@ -1,0 +1,133 @@
+"""GPU checks of the two forms beside plain fp32 MTTKRP: bf16 factor
+gathers with fp32 accumulation, and the differentiable sparse CP loss with the
+fused residual + MTTKRP backward."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_factors, hip_mttkrp, log, oracle_mttkrp, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2507_15121_amd import api, synth  # noqa: E402
+from paper_2507_15121_amd.autograd import SparseCPLoss  # noqa: E402
+
+
+# ------------------------------------------------------------------ bfloat16
+
+@pytest.mark.parametrize("rank", [32, 64, 128, 5, 40])
+def test_bf16_factors(rank):
+    dims = (20000, 5000, 3000)
+    st = synth.tensor(dims, 80000, "zipf", 1.1, 0.05, seed=21)
+    factors = synth.factors(dims, rank, seed=21)
+    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=512)
+    dbf = dev_factors(factors, torch.bfloat16)
+    for w, f in enumerate(factors):
+        bits = dbf[w].view(torch.int16).cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(bits, oracle.bf16_rne(f))  # torch RNE == oracle RNE
+    rounded = [oracle.bf16_to_f32(oracle.bf16_rne(f)) for f in factors]
+    for d in range(3):
+        got = hip_mttkrp(t, d, dbf, bf16=True)
+        assert not np.isnan(got).any()
+        e_round = rel(got, oracle_mttkrp(st.idx, st.val, dims, rounded, d))
+        e_full = rel(got, oracle_mttkrp(st.idx, st.val, dims, factors, d))
+        log("bf16 R=%d mode %d: vs rounded %.2e, vs fp32 factors %.2e" % (rank, d, e_round, e_full))
+        assert e_round <= 1e-5   # fp32 accumulation kept
+        assert e_full <= 1e-2    # bf16 gather error bar
+    t.close()
+
+
+def test_bf16_integer_exact():
+    rng = np.random.default_rng(3)
+    dims = (3000, 1500, 700)
+    st = synth.tensor(dims, 40000, "zipf", 1.2, 0.1, seed=3)
+    val = rng.integers(1, 5, st.nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, (d, 64)).astype(np.float32) for d in dims]
+    t = api.Tensor(st.idx, val, dims, chunk_nnz=64)
+    dbf = dev_factors(factors, torch.bfloat16)
+    for d in range(3):
+        np.testing.assert_array_equal(hip_mttkrp(t, d, dbf, bf16=True),
+                                      oracle_mttkrp(st.idx, val, dims, factors, d).astype(np.float32))
+    t.close()
+
+
+# ------------------------------------------------------------ CP loss / grad
+
+def _problem(dims, nnz, rank, seed, hot=0.0):
+    st = synth.tensor(dims, nnz, "zipf", 1.2, hot, seed=seed)
+    rng = np.random.default_rng(seed)
+    factors = [(rng.uniform(-1, 1, (d, rank)) * 0.5).astype(np.float32) for d in dims]
+    return st, factors
+
+
+@pytest.mark.parametrize("dims,rank", [((3000, 2000, 500, 100), 32), ((2000, 1500, 800), 16),
+                                       ((500, 400, 300), 64), ((400, 300, 200), 5)])
+def test_cp_loss_and_grad_vs_oracle(dims, rank):
+    st, factors = _problem(dims, 40000, rank, seed=rank, hot=0.05)
+    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+    dfac = dev_factors(factors)
+    loss = api.cp_loss(t, dfac)
+    ref_loss, _ = oracle.cp_loss(st.idx, st.val, factors)
+    log("loss %.9e ref %.9e" % (float(loss), ref_loss))
+    assert abs(float(loss) - ref_loss) <= 1e-5 * abs(ref_loss)
+    for d in range(len(dims)):
+        g = api.cp_grad(t, d, dfac, -2.0 * 0.75).cpu().numpy()
+        ref = oracle.cp_grad(st.idx, st.val, dims, factors, d, grad_out=0.75)
+        e = rel(g, ref)
+        log("  grad mode %d rel %.2e" % (d, e))
+        assert e <= 1e-5
+    t.close()
+
+
+def test_autograd_function_matches_oracle_and_skips_unneeded_grads():
+    dims = (2000, 1000, 300, 50)
+    st, factors = _problem(dims, 30000, 32, seed=5)
+    t = api.Tensor(st.idx, st.val, dims)
+    dfac = [f.requires_grad_(w != 2) for w, f in enumerate(dev_factors(factors))]
+    L = SparseCPLoss.apply(t, *dfac)
+    assert L.dtype == torch.float64 and L.dim() == 0
+    (3.0 * L).backward()
+    assert dfac[2].grad is None
+    for d in (0, 1, 3):
+        ref = oracle.cp_grad(st.idx, st.val, dims, factors, d, grad_out=3.0)
+        assert rel(dfac[d].grad.cpu().numpy(), ref) <= 1e-5
+    t.close()
+
+
+def test_zero_residual_gives_zero_loss_and_grad():
+    dims = (500, 300, 200)
+    rng = np.random.default_rng(7)
+    idx, _ = synth.coords(dims, 20000, "zipf", 1.1, seed=7)
+    factors = [rng.integers(-2, 3, (d, 16)).astype(np.float32) for d in dims]
+    val = oracle.cp_model(idx, factors).astype(np.float32)  # exact small integers
+    t = api.Tensor(idx, val, dims)
+    dfac = dev_factors(factors)
+    assert float(api.cp_loss(t, dfac)) == 0.0
+    for d in range(3):
+        assert not api.cp_grad(t, d, dfac, -2.0).cpu().numpy().any()
+    t.close()
+
+
+def test_directional_finite_difference():
+    # [L(A + eps V) - L(A - eps V)] / (2 eps) against <grad L, V>, loss summed in fp64
+    dims = (5000, 2000, 500, 100)
+    st, factors = _problem(dims, 100000, 32, seed=9)
+    t = api.Tensor(st.idx, st.val, dims)
+    rng = np.random.default_rng(10)
+    V = [rng.uniform(-1, 1, f.shape).astype(np.float32) for f in factors]
+    dfac = [f.requires_grad_() for f in dev_factors(factors)]
+    L = SparseCPLoss.apply(t, *dfac)
+    L.backward()
+    dirderiv = sum(float((f.grad * torch.from_numpy(v).cuda()).sum(dtype=torch.float64))
+                   for f, v in zip(dfac, V))
+    eps = 1e-3
+    plus = dev_factors([f + eps * v for f, v in zip(factors, V)])
+    minus = dev_factors([f - eps * v for f, v in zip(factors, V)])
+    fd = (float(api.cp_loss(t, plus)) - float(api.cp_loss(t, minus))) / (2 * eps)
+    log("directional derivative %.6e, central difference %.6e" % (dirderiv, fd))
+    assert abs(fd - dirderiv) <= 1e-3 * abs(dirderiv)
+    t.close()

@@ -1,0 +1,96 @@
+"""Full-size parity: the 200M-nonzero Zipf tensor (10M x 5M x 2M, R=32) in the
+launch configuration the benchmark times, checked on sampled output rows that
+the oracle computes one by one (the heaviest row of each mode plus random
+touched rows), and on whole-output properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2507_15121_amd import api, synth  # noqa: E402
+
+
+def _sample_rows(st, d, rng, n):
+    counts = np.bincount(st.idx[d], minlength=st.dims[d])
+    touched = np.flatnonzero(counts)
+    rows = rng.choice(touched, size=min(n, touched.size), replace=False)
+    rows = np.unique(np.concatenate([rows, [int(np.argmax(counts))]]))
+    untouched = np.flatnonzero(counts == 0)
+    return rows, counts, untouched
+
+
+def _oracle_rows(st, factors64, d, rows, R):
+    lut = np.full(st.dims[d], -1, dtype=np.int64)
+    lut[rows] = np.arange(rows.size)
+    m = lut[st.idx[d]] >= 0
+    sub = st.idx[:, m].copy()
+    sub[d] = lut[sub[d]]
+    dims = list(st.dims)
+    dims[d] = rows.size
+    fs = list(factors64)
+    fs[d] = np.zeros((rows.size, R))
+    return oracle.mttkrp(sub, st.val[m], dims, fs, d)
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = synth.WORKLOADS["zipf3-10Mx5Mx2M-200M"]
+    log("generating %s" % w.name)
+    st = synth.workload(w.name)
+    factors = synth.factors(st.dims, w.rank)
+    log("building layouts")
+    T = api.Tensor(st.idx, st.val, st.dims)
+    yield st, factors, T, w.rank
+    T.close()
+
+
+def test_fullsize_fp32_sampled_rows(big):
+    st, factors, T, R = big
+    dfac = [torch.from_numpy(f).cuda() for f in factors]
+    f64 = [f.astype(np.float64) for f in factors]
+    rng = np.random.default_rng(1)
+    for d in range(3):
+        out = torch.full((st.dims[d], R), float("nan"), device="cuda")
+        api.mttkrp(T, d, [None if w == d else f for w, f in enumerate(dfac)], out=out)
+        torch.cuda.synchronize()
+        assert not torch.isnan(out).any().item(), "mode %d left rows unwritten" % d
+        rows, counts, untouched = _sample_rows(st, d, rng, 300)
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        e = oracle.rel_fro(got, _oracle_rows(st, f64, d, rows, R))
+        heavy = int(np.argmax(counts))
+        k = int(np.searchsorted(rows, heavy))
+        eh = oracle.rel_fro(got[k:k + 1], _oracle_rows(st, f64, d, np.array([heavy]), R))
+        log("mode %d: sampled rel %.2e, heaviest row (%d nnz) rel %.2e" % (d, e, counts[heavy], eh))
+        assert e <= 1e-5 and eh <= 1e-5
+        if untouched.size:
+            z = out[torch.from_numpy(untouched[:100000]).cuda()]
+            assert not z.any().item()
+        # whole-output property: sum_i Y_d[i,r] A_d[i,r] = sum_k val_k prod_w A_w[i_w(k),r]
+        # does not depend on d
+        prod = out.double() * dfac[d].double()
+        inv, scale = prod.sum(0).cpu().numpy(), prod.abs().sum(0).cpu().numpy()
+        if d == 0:
+            inv0, scale0 = inv, scale
+        else:
+            assert np.all(np.abs(inv - inv0) <= 1e-5 * (scale + scale0))
+
+
+def test_fullsize_bf16_sampled_rows(big):
+    st, factors, T, R = big
+    dbf = [torch.from_numpy(f).cuda().to(torch.bfloat16) for f in factors]
+    f64 = [f.astype(np.float64) for f in factors]
+    rng = np.random.default_rng(2)
+    for d in range(3):
+        out = api.mttkrp_bf16(T, d, [None if w == d else f for w, f in enumerate(dbf)])
+        rows, _, _ = _sample_rows(st, d, rng, 200)
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        e = oracle.rel_fro(got, _oracle_rows(st, f64, d, rows, R))
+        log("bf16 mode %d: sampled rel %.2e vs fp64 oracle on fp32 factors" % (d, e))
+        assert e <= 1e-2

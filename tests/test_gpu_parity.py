@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: bit-exact for layouts and chunk flags; relative Frobenius error
+<= 1e-5 for fp32 MTTKRP; bit-exact for integer-valued inputs, whose sums are
+exact in fp32 in any order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev_factors, hip_mttkrp, log, oracle_mttkrp, rel, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2507_15121_amd import api, synth  # noqa: E402
+
+TOL = 1e-5
+
+
+def _tensor(idx, val, dims, **kw):
+    return api.Tensor(idx, val, dims, **kw)
+
+
+def _check_all_modes(idx, val, dims, factors, tol=TOL, **kw):
+    t = _tensor(idx, val, dims, **kw)
+    dfac = dev_factors(factors)
+    errs = []
+    for d in range(len(dims)):
+        got = hip_mttkrp(t, d, dfac)
+        ref = oracle_mttkrp(idx, val, dims, factors, d)
+        assert not np.isnan(got).any(), "mode %d left rows unwritten" % d
+        e = rel(got, ref)
+        errs.append(e)
+        assert e <= tol, "mode %d rel err %.3e" % (d, e)
+    t.close()
+    return errs
+
+
+@pytest.mark.parametrize("rank", [16, 32, 64])
+def test_uniform_1000x800x600_all_modes(rank):
+    w = synth.WORKLOADS["uniform3-1000x800x600-100k"]
+    st = synth.workload(w.name)
+    factors = synth.factors(st.dims, rank)
+    log("uniform 100k R=%d" % rank)
+    errs = _check_all_modes(st.idx, st.val, st.dims, factors)
+    log("  rel errs %s" % errs)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 64, 4096])
+def test_zipf_small_with_hot_slice(chunk):
+    dims = (20000, 5000, 3000)
+    st = synth.tensor(dims, 60000, "zipf", 1.1, 0.05, seed=11)
+    factors = synth.factors(dims, 32, seed=11)
+    log("zipf 60k hot chunk=%d" % chunk)
+    _check_all_modes(st.idx, st.val, dims, factors, chunk_nnz=chunk)
+
+
+def _int_problem(rng, dims, nnz, rank, hot=0.0):
+    st = synth.tensor(dims, nnz, "zipf", 1.2, hot, seed=int(rng.integers(1 << 30)))
+    val = rng.integers(1, 5, size=nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, size=(d, rank)).astype(np.float32) for d in dims]
+    return st.idx, val, factors
+
+
+@pytest.mark.parametrize("chunk", [7, 64, 4096])
+def test_integer_inputs_bit_exact_and_stable(chunk):
+    rng = np.random.default_rng(chunk)
+    dims = (3000, 1500, 700)
+    idx, val, factors = _int_problem(rng, dims, 50000, 32, hot=0.1)
+    t = _tensor(idx, val, dims, chunk_nnz=chunk)
+    dfac = dev_factors(factors)
+    for d in range(3):
+        ref = oracle_mttkrp(idx, val, dims, factors, d)
+        assert np.abs(ref).max() < 2 ** 24
+        first = hip_mttkrp(t, d, dfac)
+        np.testing.assert_array_equal(first, ref.astype(np.float32))
+        for _ in range(9):
+            again = hip_mttkrp(t, d, dfac)
+            assert np.array_equal(again.view(np.uint32), first.view(np.uint32))
+    t.close()
+
+
+@pytest.mark.parametrize("dims,rank", [((40, 30), 32), ((30, 20, 10, 8), 32), ((12, 10, 8, 6, 5), 16),
+                                       ((9, 8, 7, 6, 5, 4), 8), ((6, 5, 5, 4, 4, 3, 3, 2), 4)])
+def test_orders_2_to_8(dims, rank):
+    rng = np.random.default_rng(len(dims))
+    nnz = min(2000, int(np.prod(dims)) // 2)
+    idx, _ = synth.coords(dims, nnz, "uniform", seed=len(dims))
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [rng.uniform(-1, 1, (d, rank)).astype(np.float32) for d in dims]
+    log("order %d rank %d" % (len(dims), rank))
+    _check_all_modes(idx, val, dims, factors, chunk_nnz=64)
+
+
+@pytest.mark.parametrize("rank", [1, 3, 5, 8, 20, 48, 100, 128, 200])
+def test_ranks_vector_and_column_tile_paths(rank):
+    dims = (500, 400, 300)
+    st = synth.tensor(dims, 20000, "zipf", 1.1, 0.0, seed=rank)
+    factors = synth.factors(dims, rank, seed=rank)
+    log("rank %d" % rank)
+    _check_all_modes(st.idx, st.val, dims, factors, chunk_nnz=256)
+
+
+def test_single_nonzero_and_single_row_modes():
+    dims = (7, 1, 5)
+    idx = np.array([[3], [0], [4]], np.int32)
+    val = np.array([1.5], np.float32)
+    rng = np.random.default_rng(2)
+    factors = [rng.uniform(-1, 1, (d, 32)).astype(np.float32) for d in dims]
+    _check_all_modes(idx, val, dims, factors)
+
+
+def test_all_nonzeros_in_one_slice_many_chunks():
+    rng = np.random.default_rng(3)
+    dims = (50, 4000, 3000)
+    nnz = 30000
+    lin = np.sort(rng.choice(4000 * 3000, size=nnz, replace=False))
+    idx = np.stack([np.full(nnz, 17), lin // 3000, lin % 3000]).astype(np.int32)
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [rng.uniform(-1, 1, (d, 32)).astype(np.float32) for d in dims]
+    for ch in (1, 7, 100):
+        log("one slice chunk=%d" % ch)
+        _check_all_modes(idx, val, dims, factors, chunk_nnz=ch)
+
+
+def test_empty_tensor_zeroes_output():
+    dims = (100, 70, 3)
+    idx = np.zeros((3, 0), np.int32)
+    val = np.zeros(0, np.float32)
+    t = _tensor(idx, val, dims)
+    dfac = dev_factors([np.ones((d, 16), np.float32) for d in dims])
+    for d in range(3):
+        out = hip_mttkrp(t, d, dfac)
+        assert out.shape == (dims[d], 16) and not out.any() and not np.isnan(out).any()
+    t.close()
+
+
+def test_long_untouched_row_runs():
+    # few nonzeros in huge modes: most output rows are zero, in long runs
+    rng = np.random.default_rng(4)
+    dims = (200000, 64, 100000)
+    nnz = 500
+    idx = np.stack([rng.integers(0, d, nnz) for d in dims]).astype(np.int32)
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [rng.uniform(-1, 1, (d, 16)).astype(np.float32) for d in dims]
+    _check_all_modes(idx, val, dims, factors, chunk_nnz=32)
+
+
+def test_duplicates_and_unsorted_input():
+    rng = np.random.default_rng(5)
+    dims = (300, 200, 100)
+    nnz = 20000
+    idx = np.stack([rng.integers(0, d, nnz) for d in dims]).astype(np.int32)  # duplicates, unsorted
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [rng.uniform(-1, 1, (d, 32)).astype(np.float32) for d in dims]
+    _check_all_modes(idx, val, dims, factors, chunk_nnz=128)
+
+
+@pytest.mark.parametrize("chunk", [7, 4096])
+def test_device_layout_bit_exact(chunk):
+    st = synth.tensor((2000, 900, 400), 30000, "zipf", 1.1, 0.05, seed=6)
+    rng = np.random.default_rng(6)
+    p = rng.permutation(st.nnz)
+    idx, val = st.idx[:, p], st.val[p]  # shuffled input
+    t = _tensor(idx, val, st.dims, chunk_nnz=chunk, keep_perm=True)
+    for d in range(3):
+        lay = t.layout(d, perm=True)
+        ref = oracle.layout(idx, d, chunk)
+        np.testing.assert_array_equal(lay["perm"], ref["perm"])
+        np.testing.assert_array_equal(lay["out_idx"], ref["out_idx"])
+        np.testing.assert_array_equal(lay["in_idx"], ref["in_idx"])
+        np.testing.assert_array_equal(lay["values"].view(np.uint32), val[ref["perm"]].view(np.uint32))
+        np.testing.assert_array_equal(lay["flags"], ref["flags"])
+    assert t.touched == tuple(len(np.unique(idx[w])) for w in range(3))
+    t.close()
+
+
+def test_non_default_stream_and_reuse_of_output():
+    st = synth.tensor((3000, 2000, 1000), 40000, "zipf", 1.1, 0.0, seed=8)
+    factors = synth.factors(st.dims, 32, seed=8)
+    t = _tensor(st.idx, st.val, st.dims)
+    dfac = dev_factors(factors)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = hip_mttkrp(t, 1, dfac, stream=s)
+    ref = oracle_mttkrp(st.idx, st.val, st.dims, factors, 1)
+    assert rel(got, ref) <= TOL
+    t.close()
+
+
+def test_call_errors_on_device():
+    from ctypes import c_void_p
+    st = synth.tensor((300, 200, 100), 2000, "zipf", 1.1, 0.0, seed=9)
+    t = _tensor(st.idx, st.val, st.dims)
+    dfac = dev_factors(synth.factors(st.dims, 32, seed=9))
+    out = torch.empty((300, 32), device="cuda")
+    with pytest.raises(ValueError):
+        api.mttkrp(t, 0, [None, dfac[1][1:], dfac[2]], out=out)  # wrong shape, caught in python
+    L = api.lib()
+    ptrs = (c_void_p * 3)(None, dfac[1].data_ptr() + 4, dfac[2].data_ptr())
+    assert L.amped_mttkrp(t.handle, 0, 32, ptrs, c_void_p(out.data_ptr()), None) == api.ERR_INVALID
+    ptrs = (c_void_p * 3)(None, dfac[1].data_ptr(), dfac[2].data_ptr())
+    assert L.amped_mttkrp(t.handle, 3, 32, ptrs, c_void_p(out.data_ptr()), None) == api.ERR_INVALID
+    assert L.amped_mttkrp(t.handle, 0, 0, ptrs, c_void_p(out.data_ptr()), None) == api.ERR_INVALID
+    assert L.amped_mttkrp(t.handle, 0, 32, ptrs, None, None) == api.ERR_INVALID
+    ptrs = (c_void_p * 3)(None, None, dfac[2].data_ptr())
+    assert L.amped_mttkrp(t.handle, 0, 32, ptrs, c_void_p(out.data_ptr()), None) == api.ERR_INVALID
+    # the fused gradient needs the output mode's factor too
+    ptrs = (c_void_p * 3)(None, dfac[1].data_ptr(), dfac[2].data_ptr())
+    assert L.amped_cp_grad(t.handle, 0, 32, ptrs, 1.0, c_void_p(out.data_ptr()), None) == api.ERR_INVALID
+    assert "factors[0]" in L.amped_last_error().decode()
+    t.close()
