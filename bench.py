@@ -21,6 +21,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MTTKRP nnz/s + achieved HBM TB/s per mode; FP32 vs BF16-factor at stated tol"
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(workload, lib_path):
+    """HBM-side bytes per launch of the fp32 kernel from a committed counter
+    summary (profiles/mttkrp_<workload>_R*_traffic.md), used only while the
+    loaded library is the build those counters were taken on."""
+    import glob
+    import hashlib
+    sha = hashlib.sha256(open(lib_path, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(PROFILES, "mttkrp_%s_R*_traffic.md" % workload)):
+        fields = {}
+        for line in open(path):
+            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "library_sha256"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("library_sha256") == sha and "traffic_bytes_per_launch" in fields:
+            return float(fields["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
 
 
 def log(msg):
@@ -40,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and CP loss/grad forms")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     return ap.parse_args()
@@ -218,21 +237,24 @@ def main():
         crng = np.random.default_rng(11)
 
         def run_sample(S):
-            sel = np.sort(crng.choice(st.nnz, size=S, replace=False))
+            sel = np.sort(crng.choice(st.nnz, size=S, replace=False)) if S else np.zeros(0, np.int64)
             sub, sv = np.ascontiguousarray(st.idx[:, sel]), val64[sel]
             c0 = time.perf_counter()
             for d in range(N):
                 oracle.mttkrp(sub, sv, st.dims, factors64, d)
             return time.perf_counter() - c0
-        S0 = min(st.nnz, 200_000)
-        t_probe = run_sample(S0)
-        S = int(min(st.nnz, max(S0, S0 * args.cpu_seconds / max(t_probe, 1e-6))))
-        t_cpu = run_sample(S) if S > S0 else t_probe
+        # time model t(S) = a + b*S (a: zeroing the full-size outputs)
+        t_zero = run_sample(0)
+        S0 = min(st.nnz, 1_000_000)
+        b_per = max(run_sample(S0) - t_zero, 1e-9) / S0
+        S = int(min(st.nnz, max(S0, (args.cpu_seconds - t_zero) / b_per)))
+        t_cpu = run_sample(S)
         cpu = {"value": N * S / t_cpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
                "sample": "%d random nonzeros of the same tensor, all %d modes, full-size factors and "
-                         "outputs, float64, one thread; %.1fs" % (S, N, t_cpu)}
+                         "outputs (zeroing included), float64, one thread; %.1fs" % (S, N, t_cpu)}
         log("cpu baseline %s" % cpu)
 
+    traffic, traffic_src = measured_traffic(wl.name, api.LIB_PATH)
     value = N * st.nnz / (ms_step * 1e-3)
     res = {
         "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
@@ -243,7 +265,9 @@ def main():
                    "chunk_nnz": T.chunk_nnz, "seed": seed,
                    "value_is": "modes x nnz / all-mode step time"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src,
                      "kernel": "mttkrp_kernel (fp32)",
                      "bytes_model": "per mode: nnz*(4N+4) + sum_{w!=d} touched_w*R*4 + I_d*R*4"},
         "per_mode": per_mode,

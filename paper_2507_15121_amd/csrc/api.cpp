@@ -200,7 +200,7 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     }
     // peak device bytes: the N layouts, the kept permutations, and during the
     // build the raw COO plus one permutation
-    const int64_t layout_bytes = (int64_t)order * (order + 1) * 4 * nnz;
+    const int64_t layout_bytes = (int64_t)order * (order + 1) * 4 * (nnz + 4);
     const int64_t peak = layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
                          4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8;
     if (cap > 0 && peak > cap)
@@ -254,18 +254,21 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
                             "hipMemcpy(perm)");
             ModeDev& m = t->mode[d];
             void* p = nullptr;
-            HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(out_idx)");
+            // layout arrays carry 4 padding entries so 16-byte loads of the
+            // last nonzeros stay inside the allocation
+            const size_t padded = ((size_t)nnz + 4) * 4;
+            HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(out_idx)");
             HIP_OR_FAIL(amped::launch_permute32(p, d_cols[d], static_cast<int32_t*>(d_perm), nnz, stream), "permute");
             m.out_idx = static_cast<int32_t*>(p);
             int j = 0;
             for (int w = 0; w < order; ++w) {
                 if (w == d) continue;
-                HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(in_idx)");
+                HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(in_idx)");
                 HIP_OR_FAIL(amped::launch_permute32(p, d_cols[w], static_cast<int32_t*>(d_perm), nnz, stream),
                             "permute");
                 m.in_idx[j++] = static_cast<int32_t*>(p);
             }
-            HIP_OR_FAIL(t->alloc(&p, (size_t)nnz * 4), "hipMalloc(values)");
+            HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(values)");
             HIP_OR_FAIL(amped::launch_permute32(p, d_vals, static_cast<int32_t*>(d_perm), nnz, stream), "permute");
             m.val = static_cast<float*>(p);
             if (!lay.split_rows.empty()) {

@@ -39,6 +39,26 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxIn = kMaxOrder - 1;
 
+// Tuning knobs (compile-time): sub-steps whose gathers are issued together
+// (for up to 2 input modes; half of it above), and the waves per SIMD the
+// register allocation must allow (0 = compiler's choice).
+#ifndef AMPED_UMAX
+#define AMPED_UMAX 8
+#endif
+#ifndef AMPED_FIBER
+#define AMPED_FIBER 0
+#endif
+#ifndef AMPED_MIN_WAVES
+#define AMPED_MIN_WAVES 0
+#endif
+#if AMPED_MIN_WAVES > 0
+#define AMPED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(AMPED_MIN_WAVES)))
+#else
+#define AMPED_OCCUPANCY
+#endif
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
 struct KParams {
     const int32_t* out_idx;
     const int32_t* in_idx[kMaxIn];
@@ -250,11 +270,11 @@ __global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, in
 // KIND 0: MTTKRP.  KIND 1: scale * MTTKRP of the residuals val - CP model,
 // recomputed per nonzero from all factor rows.
 template <int NIN, int LPR, int RPL, typename T, int KIND>
-__global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
+__global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
 {
     constexpr int G = 64 / LPR;                       // nonzero groups per wave
     constexpr int RT = LPR * RPL;                     // columns per wave row
-    constexpr int UMAX = (NIN <= 2) ? 8 : 4;
+    constexpr int UMAX = (NIN <= 2) ? AMPED_UMAX : (AMPED_UMAX + 1) / 2;
     constexpr int MPL = (LPR < UMAX) ? UMAX / LPR : 1;  // nonzeros of metadata per lane
     constexpr int TS = LPR * MPL;                     // nonzeros per group per tile
     constexpr int U = (TS < UMAX) ? TS : UMAX;        // sub-steps per gather batch
@@ -501,16 +521,370 @@ __global__ void __launch_bounds__(kBlock) mttkrp_kernel(const KParams p)
     }
 }
 
+// ----------------------------------------------------- pipelined MTTKRP kernel
+// Same work decomposition and output rules as mttkrp_kernel, with the memory
+// accesses software-pipelined:
+//  * the nonzero metadata of tile tau+2 is loaded (VGPRs) while tile tau is
+//    processed and parked in a 2-slot LDS ring at the start of tile tau+1, so
+//    its latency is hidden behind at least two batches of work;
+//  * the factor-row gathers of batch q+1 are issued before batch q is
+//    consumed (two register buffers), so a wave always has a batch in flight.
+// A tile is TS >= 2U nonzeros per group, a batch U nonzeros per group.
+template <int NIN, int LPR, int RPL, typename T, int KIND>
+__global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_pipe_kernel(const KParams p)
+{
+    constexpr int G = 64 / LPR;
+    constexpr int RT = LPR * RPL;
+    constexpr int UMAX = (NIN <= 2) ? AMPED_UMAX : (AMPED_UMAX + 1) / 2;
+    constexpr int U = UMAX;                                      // nonzeros per group per batch
+    constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
+    constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
+    constexpr int NB = TS / U;                                   // batches per tile (even)
+    constexpr int NF = NIN + 2;                                  // key, input indices, value
+    constexpr bool VEC = RPL > 1;
+    // fibers: consecutive nonzeros with the same output index and the same
+    // first input index share that input row; it is gathered and multiplied
+    // once per fiber (the remaining product is summed over the fiber first)
+    constexpr bool FIBER = (KIND == 0) && (NIN >= 2) && (AMPED_FIBER != 0);
+    using RowT = Row<T, RPL>;
+    using OwnRow = Row<float, (KIND == 1) ? RPL : 1>;
+    static_assert(KIND == 0 || std::is_same<T, float>::value, "residual form is fp32 only");
+    static_assert(NB % 2 == 0, "batches per tile must be even");
+
+    __shared__ int s_key[kWaves][2 * G];
+    __shared__ int s_ext[kWaves][2 * G];
+    __shared__ float s_acc[kWaves][2 * G][RT];
+    __shared__ int s_meta[kWaves][2][NF][G * TS];               // [slot][field][group*TS + j]
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane / LPR;
+    const int s = lane % LPR;
+    const bool lane_on = VEC || (s * RPL < p.ncols);
+    const int c = p.col0 + (lane_on ? s * RPL : 0);
+    const int64_t ld = VEC ? (int64_t)RT : p.ld;
+    const uint64_t rb = (uint64_t)ld * sizeof(T);
+    const uint64_t rb_own = (uint64_t)ld * sizeof(float);
+    const float oscale = (KIND == 1) ? p.scale : 1.0f;
+    const char* lbase[NIN];
+#pragma unroll
+    for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(T);
+    const char* obase = (KIND == 1) ? reinterpret_cast<const char*>(p.own + c) : nullptr;
+
+    for (;;) {
+        const int chunk = pop_chunk(p.queue, lane);
+        if (chunk >= p.n_chunks) break;
+        const int64_t cs = (int64_t)chunk * p.chunk;
+        const int64_t ce = min(cs + p.chunk, p.nnz);
+        const int64_t Lg = ((ce - cs + G * TS - 1) / (G * TS)) * TS;
+        const int64_t gs = cs + g * Lg;
+        const int64_t ge = min(gs + Lg, ce);
+        const bool gon = gs < ge;
+        const int ntiles = (int)(Lg / TS);
+        const int nbatch = ntiles * NB;
+
+        if (s == 0) {
+            s_key[wv][2 * g] = -1;
+            s_key[wv][2 * g + 1] = -1;
+        }
+        int open_key = -1;
+        bool open_first = true;
+        bool left_shared = false;
+        float acc[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+        if (gon) {
+            const int first = p.out_idx[gs];
+            const int prev = gs > 0 ? p.out_idx[gs - 1] : -1;
+            left_shared = (prev == first);
+            if (lane_on && first - prev - 1 > 0 && first - prev - 1 < kGapInKernel)
+                zero_rows<RPL>(p.out, prev + 1, first, ld, c);
+            open_key = first;
+        }
+        bool parked = false;
+        auto flush_mid = [&]() {
+            if (open_first && left_shared) {
+                parked = true;
+                float* dst = &s_acc[wv][2 * g][s * RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
+                if (s == 0) {
+                    s_key[wv][2 * g] = open_key;
+                    s_ext[wv][2 * g] = (g == 0) ? 1 : 0;
+                }
+            } else if (lane_on) {
+                float v[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
+                store_cols<RPL>(p.out, open_key, ld, c, v);
+            }
+        };
+
+        // ---- metadata: VGPR staging -> LDS ring.  Lane s of group g holds
+        // nonzeros gs + t*TS + k*4*LPR + 4s .. +3 of each field, read with one
+        // 16-byte load when chunk starts are 4-aligned (the layout arrays are
+        // padded by 4 entries, so such a load never leaves the allocation).
+        const bool vec_meta = (p.chunk & 3) == 0;
+        i32x4 vm[Q4][NF];
+        auto load_meta = [&](int t) {
+#pragma unroll
+            for (int kq = 0; kq < Q4; ++kq) {
+                const int64_t mp = gs + (int64_t)t * TS + kq * 4 * LPR + 4 * s;
+                const bool on = gon && t < ntiles && mp < ge;
+                if (vec_meta) {
+                    const i32x4 z = {0, 0, 0, 0};
+                    vm[kq][0] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.out_idx + mp)) : z;
+#pragma unroll
+                    for (int w = 0; w < NIN; ++w)
+                        vm[kq][1 + w] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.in_idx[w] + mp)) : z;
+                    vm[kq][NF - 1] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.val + mp)) : z;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool one = gon && t < ntiles && mp + e < ge;
+                        vm[kq][0][e] = one ? p.out_idx[mp + e] : 0;
+#pragma unroll
+                        for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = one ? p.in_idx[w][mp + e] : 0;
+                        vm[kq][NF - 1][e] = one ? __float_as_int(p.val[mp + e]) : 0;
+                    }
+                }
+            }
+        };
+        auto park_meta = [&](int slot) {
+#pragma unroll
+            for (int kq = 0; kq < Q4; ++kq)
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    *reinterpret_cast<i32x4*>(&s_meta[wv][slot][f][g * TS + kq * 4 * LPR + 4 * s]) = vm[kq][f];
+            wave_lds_sync();
+        };
+        auto meta_at = [&](int slot, int f, int j) { return s_meta[wv][slot][f][g * TS + j]; };
+
+        typename RowT::Raw rawA[U][NIN], rawB[U][NIN];
+        typename OwnRow::Raw ownA[U], ownB[U];
+
+        // issue the gathers of batch q (idle entries read row 0)
+        auto issue = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U], int& fmask) {
+            const int t = q / NB;
+            const int j0 = (q % NB) * U;
+            const int slot = t & 1;
+            const int64_t base = gs + (int64_t)t * TS + j0;
+            fmask = 0;
+            static_for<U>([&](auto ju) {
+                constexpr int JU = decltype(ju)::value;
+                const bool valid = gon && (base + JU < ge);
+                bool fend = true;
+                if constexpr (FIBER) {
+                    // the next nonzero of the run is in this tile or at the start of the next
+                    const bool nvalid = gon && (base + JU + 1 < ge);
+                    const int nj = j0 + JU + 1;
+                    const int nslot = (nj < TS) ? slot : (slot ^ 1);
+                    const int nidx = (nj < TS) ? nj : 0;
+                    fend = !nvalid || meta_at(nslot, 0, nidx) != meta_at(slot, 0, j0 + JU) ||
+                           meta_at(nslot, 1, nidx) != meta_at(slot, 1, j0 + JU);
+                    fmask |= (fend ? 1 : 0) << JU;
+                }
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) {
+                    const int ix = valid ? meta_at(slot, 1 + w, j0 + JU) : 0;
+                    if (FIBER && w == 0 && !fend) {
+                        raw[JU][w] = RowT::zero();
+                    } else {
+                        if constexpr (VEC) raw[JU][w] = RowT::load(lbase[w], ix, rb);
+                        else raw[JU][w] = lane_on ? RowT::load(lbase[w], ix, rb) : RowT::zero();
+                    }
+                }
+                if constexpr (KIND == 1) {
+                    const int k = valid ? meta_at(slot, 0, j0 + JU) : 0;
+                    if constexpr (VEC) own[JU] = OwnRow::load(obase, k, rb_own);
+                    else own[JU] = lane_on ? OwnRow::load(obase, k, rb_own) : OwnRow::zero();
+                }
+            });
+        };
+
+        // consume batch q from its buffers: Hadamard, scale, running row sum
+        float facc[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) facc[i] = 0.f;
+        auto consume = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U], int fmask) {
+            const int t = q / NB;
+            const int j0 = (q % NB) * U;
+            const int slot = t & 1;
+            const int64_t base = gs + (int64_t)t * TS + j0;
+            static_for<U>([&](auto ju) {
+                constexpr int JU = decltype(ju)::value;
+                const bool valid = gon && (base + JU < ge);
+                const int key = meta_at(slot, 0, j0 + JU);
+                const float val = __int_as_float(meta_at(slot, NF - 1, j0 + JU));
+                if constexpr (FIBER) {
+                    // facc += val * prod_{w>=1} rows; at a fiber end acc += facc * row_0
+                    float prod[RPL];
+                    RowT::unpack(raw[JU][1], prod);
+#pragma unroll
+                    for (int w = 2; w < NIN; ++w) {
+                        float rw[RPL];
+                        RowT::unpack(raw[JU][w], rw);
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) prod[i] *= rw[i];
+                    }
+                    if (valid) {
+                        if (key != open_key) {
+                            flush_mid();
+                            if (lane_on && key - open_key - 1 > 0 && key - open_key - 1 < kGapInKernel)
+                                zero_rows<RPL>(p.out, open_key + 1, key, ld, c);
+#pragma unroll
+                            for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+                            open_key = key;
+                            open_first = false;
+                        }
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) facc[i] = fmaf(val, prod[i], facc[i]);
+                        if ((fmask >> JU) & 1) {
+                            float r0[RPL];
+                            RowT::unpack(raw[JU][0], r0);
+#pragma unroll
+                            for (int i = 0; i < RPL; ++i) {
+                                acc[i] = fmaf(facc[i], r0[i], acc[i]);
+                                facc[i] = 0.f;
+                            }
+                        }
+                    }
+                    return;
+                }
+                float prod[RPL];
+                {
+                    float r0[RPL];
+                    RowT::unpack(raw[JU][0], r0);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) prod[i] = r0[i];
+                }
+#pragma unroll
+                for (int w = 1; w < NIN; ++w) {
+                    float rw[RPL];
+                    RowT::unpack(raw[JU][w], rw);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) prod[i] *= rw[i];
+                }
+                float coef = val;
+                if constexpr (KIND == 1) {
+                    float ow[RPL];
+                    OwnRow::unpack(own[JU], ow);
+                    float part = 0.f;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
+                    coef = val - group_sum<LPR>(part);
+                }
+                if (valid) {
+                    if (key != open_key) {
+                        flush_mid();
+                        if (lane_on && key - open_key - 1 > 0 && key - open_key - 1 < kGapInKernel)
+                            zero_rows<RPL>(p.out, open_key + 1, key, ld, c);
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+                        open_key = key;
+                        open_first = false;
+                    }
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) acc[i] = fmaf(coef, prod[i], acc[i]);
+                }
+            });
+        };
+
+        if (nbatch > 0) {
+            int fA = 0, fB = 0;
+            load_meta(0);
+            park_meta(0);
+            load_meta(1);
+            park_meta(1);  // the fiber test of tile 0 looks at the first entry of tile 1
+            load_meta(2);
+            issue(0, rawA, ownA, fA);
+#pragma unroll 1
+            for (int q = 0; q < nbatch; q += 2) {
+                if ((q % NB) == 0 && q > 0) {
+                    // start of tile t = q/NB (t >= 1): tile t+1 goes to the ring, tile t+2 is loaded
+                    const int t = q / NB;
+                    park_meta((t + 1) & 1);
+                    load_meta(t + 2);
+                }
+                issue(q + 1, rawB, ownB, fB);
+                consume(q, rawA, ownA, fA);
+                if (q + 2 < nbatch) issue(q + 2, rawA, ownA, fA);
+                consume(q + 1, rawB, ownB, fB);
+            }
+        }
+
+        // end of the run: the open segment
+        if (gon) {
+            const int nextk = ge < p.nnz ? p.out_idx[ge] : -1;
+            const bool right_shared = (nextk == open_key);
+            if ((open_first && left_shared) || right_shared) {
+                float* dst = &s_acc[wv][2 * g + 1][s * RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
+                if (s == 0) {
+                    s_key[wv][2 * g + 1] = open_key;
+                    s_ext[wv][2 * g + 1] = ((open_first && left_shared && g == 0) ? 1 : 0) |
+                                           ((right_shared && ge == ce) ? 2 : 0);
+                }
+                parked = true;
+            } else if (lane_on) {
+                float v[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
+                store_cols<RPL>(p.out, open_key, ld, c, v);
+            }
+            if (ge == p.nnz && lane_on && p.rows - open_key - 1 > 0 && p.rows - open_key - 1 < kGapInKernel)
+                zero_rows<RPL>(p.out, open_key + 1, p.rows, ld, c);
+        }
+
+        if (__builtin_amdgcn_ballot_w64(parked) != 0) {
+            wave_lds_sync();
+            if (g == 0) {
+                int cur = -1, cur_ext = 0;
+                float cacc[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) cacc[i] = 0.f;
+                auto emit = [&]() {
+                    if (cur < 0 || !lane_on) return;
+                    float v[RPL];
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) v[i] = cacc[i] * oscale;
+                    if (cur_ext) atomic_cols<RPL>(p.out, cur, ld, c, v);
+                    else store_cols<RPL>(p.out, cur, ld, c, v);
+                };
+                for (int qq = 0; qq < 2 * G; ++qq) {
+                    const int k = s_key[wv][qq];
+                    if (k < 0) continue;
+                    const float* src = &s_acc[wv][qq][s * RPL];
+                    if (k != cur) {
+                        emit();
+                        cur = k;
+                        cur_ext = s_ext[wv][qq];
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) cacc[i] = src[i];
+                    } else {
+                        cur_ext |= s_ext[wv][qq];
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) cacc[i] += src[i];
+                    }
+                }
+                emit();
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 // ------------------------------------------------------------------ CP loss
 // Sum over nonzeros of (val - sum_r prod_w A_w[i_w, r])^2: per-entry work in
 // fp32, each squared residual added in fp64 by the group's first lane, one
 // fp64 atomic per wave.
 template <int NIN, int LPR, int RPL>
-__global__ void __launch_bounds__(kBlock) cp_loss_kernel(const KParams p)
+__global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY cp_loss_kernel(const KParams p)
 {
     constexpr int G = 64 / LPR;
     constexpr int RT = LPR * RPL;
-    constexpr int UMAX = (NIN <= 2) ? 8 : 4;
+    constexpr int UMAX = (NIN <= 2) ? AMPED_UMAX : (AMPED_UMAX + 1) / 2;
     constexpr int MPL = (LPR < UMAX) ? UMAX / LPR : 1;  // nonzeros of metadata per lane
     constexpr int TS = LPR * MPL;                     // nonzeros per group per tile
     constexpr int U = (TS < UMAX) ? TS : UMAX;        // sub-steps per gather batch
@@ -625,6 +999,15 @@ using KernelFn = void (*)(const KParams);
 // to 4 input modes; every other case takes the scalar column-tile path.
 constexpr int kMaxVecNin = 4;
 
+#ifndef AMPED_PIPELINE
+#define AMPED_PIPELINE 0
+#endif
+#if AMPED_PIPELINE
+#define MTTKRP_KERNEL mttkrp_pipe_kernel
+#else
+#define MTTKRP_KERNEL mttkrp_kernel
+#endif
+
 template <int NIN, typename T, int KIND>
 KernelFn pick_vec(int lpr)
 {
@@ -633,11 +1016,11 @@ KernelFn pick_vec(int lpr)
         return nullptr;
     } else {
         switch (lpr) {
-        case 4: return mttkrp_kernel<NIN, 4, RPL, T, KIND>;
-        case 8: return mttkrp_kernel<NIN, 8, RPL, T, KIND>;
-        case 16: return mttkrp_kernel<NIN, 16, RPL, T, KIND>;
+        case 4: return MTTKRP_KERNEL<NIN, 4, RPL, T, KIND>;
+        case 8: return MTTKRP_KERNEL<NIN, 8, RPL, T, KIND>;
+        case 16: return MTTKRP_KERNEL<NIN, 16, RPL, T, KIND>;
         case 32:
-            if constexpr (std::is_same<T, float>::value) return mttkrp_kernel<NIN, 32, RPL, T, KIND>;
+            if constexpr (std::is_same<T, float>::value) return MTTKRP_KERNEL<NIN, 32, RPL, T, KIND>;
             else return nullptr;
         default: return nullptr;
         }
@@ -649,11 +1032,11 @@ KernelFn pick_mttkrp_nin(FactorType ft, Kind kind, int lpr, bool scalar)
 {
     if (kind == Kind::Mttkrp) {
         if (ft == FactorType::F32)
-            return scalar ? mttkrp_kernel<NIN, 64, 1, float, 0> : pick_vec<NIN, float, 0>(lpr);
-        return scalar ? mttkrp_kernel<NIN, 64, 1, uint16_t, 0> : pick_vec<NIN, uint16_t, 0>(lpr);
+            return scalar ? MTTKRP_KERNEL<NIN, 64, 1, float, 0> : pick_vec<NIN, float, 0>(lpr);
+        return scalar ? MTTKRP_KERNEL<NIN, 64, 1, uint16_t, 0> : pick_vec<NIN, uint16_t, 0>(lpr);
     }
     if (ft != FactorType::F32) return nullptr;
-    return scalar ? mttkrp_kernel<NIN, 64, 1, float, 1> : pick_vec<NIN, float, 1>(lpr);
+    return scalar ? MTTKRP_KERNEL<NIN, 64, 1, float, 1> : pick_vec<NIN, float, 1>(lpr);
 }
 
 KernelFn pick_mttkrp(int nin, FactorType ft, Kind kind, int lpr, bool scalar)
