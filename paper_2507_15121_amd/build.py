@@ -6,6 +6,7 @@
 
 Every call recompiles.  ``python -m paper_2507_15121_amd.build`` runs it.
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -22,7 +23,7 @@ ARCH = "gfx950"
 LIB = os.path.join(HERE, "libamped.so")
 SYNTH_LIB = os.path.join(HERE, "libamped_synth.so")
 
-HIP_SOURCES = ["kernels.hip"]
+HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_loss.hip"]
 HOST_SOURCES = ["api.cpp", "layout.cpp"]
 
 HIPCC_FLAGS = [
@@ -57,17 +58,19 @@ def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None):
     lib_path = out or LIB
     bdir = build_dir or BUILD_DIR
     os.makedirs(bdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        _run([hipcc] + HIPCC_FLAGS + list(extra_hip_flags) +
-             ["-I" + INCLUDE, "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([hipcc] + HIPCC_FLAGS + list(extra_hip_flags) +
+                     ["-I" + INCLUDE, "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HOST_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        _run(["g++"] + HOST_FLAGS + ["-I" + INCLUDE, "-I" + CSRC, "-c",
-                                     os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append((["g++"] + HOST_FLAGS + ["-I" + INCLUDE, "-I" + CSRC, "-c",
+                                            os.path.join(CSRC, src), "-o", obj], obj))
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    objs = [j[1] for j in jobs]
     tmp = lib_path + ".tmp"
     _run(["g++", "-shared", "-fopenmp", "-o", tmp] + objs +
          ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64",

@@ -419,7 +419,10 @@ amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const*
     a.kind = kind;
     int j = 0;
     for (int w = 0; w < t->order; ++w)
-        if (w != mode) a.in_factors[j++] = factors[w];
+        if (w != mode) {
+            a.in_rows[j] = t->dims[w];
+            a.in_factors[j++] = factors[w];
+        }
     a.own_factor = grad ? static_cast<const float*>(factors[mode]) : nullptr;
     a.scale = scale;
     a.out = out;
@@ -467,7 +470,10 @@ amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* facto
     a.order = t->order;
     a.rank = rank;
     a.own_factor = factors[0];
-    for (int w = 1; w < t->order; ++w) a.in_factors[w - 1] = factors[w];
+    for (int w = 1; w < t->order; ++w) {
+        a.in_factors[w - 1] = factors[w];
+        a.in_rows[w - 1] = t->dims[w];
+    }
     a.loss = loss;
     a.stream = static_cast<hipStream_t>(stream);
     hipError_t e = amped::launch_cp_loss(a);

@@ -63,6 +63,7 @@ struct LaunchArgs {
     FactorType ftype = FactorType::F32;
     Kind kind = Kind::Mttkrp;
     const void* in_factors[kMaxOrder - 1] = {};    // input-mode factors, modes ascending
+    int64_t in_rows[kMaxOrder - 1] = {};           // their row counts
     const float* own_factor = nullptr;             // factor of the output mode (ResidualGrad)
     float scale = 1.0f;                            // ResidualGrad output scale
     float* out = nullptr;
@@ -82,6 +83,7 @@ struct LossArgs {
     int rank = 0;
     const float* own_factor = nullptr;
     const float* in_factors[kMaxOrder - 1] = {};
+    int64_t in_rows[kMaxOrder - 1] = {};
     double* loss = nullptr;
     hipStream_t stream = nullptr;
 };

@@ -1,0 +1,609 @@
+#pragma once
+// Device code shared by the gfx950 kernel translation units: sparse MTTKRP (Eq. 1, Sec. 2.1), its bfloat16-factor
+// form, the sparse CP loss and the fused residual + MTTKRP gradient.
+//
+// Work decomposition (one GPU's share of the paper's scheme, Sec. 3-4):
+//  * A mode's nonzeros are sorted by output index (Sec. 3.1: all nonzeros of
+//    one output index together) and cut into chunks of CH nonzeros, the
+//    equal-size inter-shard partitions of Sec. 3.1/3.2.
+//  * A persistent grid of wave64s replaces the hardware block scheduler of
+//    Sec. 4.2: each wave takes the next chunk from a device atomic counter
+//    until none is left, so skewed slices spread over all CUs.
+//  * Inside a chunk the wave is G groups of LPR lanes.  Each lane holds RPL
+//    consecutive columns of a factor row (16 bytes), so a group loads a whole
+//    row with one coalesced access.  Group g walks its own contiguous run of
+//    the chunk's nonzeros in order and keeps the running sum of the current
+//    output row in registers (the elementwise computation, EC of Sec. 3,
+//    reduced over consecutive equal output indices instead of one atomic per
+//    nonzero as in Alg. 2).
+//  * A row that starts and ends inside one group's run is written once with a
+//    plain store.  Pieces of rows that cross group boundaries are parked in
+//    LDS and summed at the end of the chunk; only rows that cross a chunk
+//    boundary are added to memory with fp32 atomics (Sec. 3.2 uses atomics
+//    between SMs), after the init kernel has zeroed them.
+//  * Untouched output rows are zeroed once: short runs by the wave that
+//    reaches them, long runs by the init kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <type_traits>
+#include <unordered_map>
+#include <utility>
+
+#include "internal.h"
+
+namespace amped {
+namespace dev {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxIn = kMaxOrder - 1;
+
+// Tuning knobs (compile-time): sub-steps whose gathers are issued together
+// (for up to 2 input modes; half of it above), and the waves per SIMD the
+// register allocation must allow (0 = compiler's choice).
+#ifndef AMPED_UMAX
+#define AMPED_UMAX 8
+#endif
+#ifndef AMPED_MIN_WAVES
+#define AMPED_MIN_WAVES 0
+#endif
+#if AMPED_MIN_WAVES > 0
+#define AMPED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(AMPED_MIN_WAVES)))
+#else
+#define AMPED_OCCUPANCY
+#endif
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+struct KParams {
+    const int32_t* out_idx;
+    const int32_t* in_idx[kMaxIn];
+    const float* val;
+    const void* fac[kMaxIn];
+    const float* own;
+    float* out;
+    double* loss;
+    int* queue;
+    int64_t nnz, chunk, n_chunks, rows;
+    int64_t ld;     // row stride of factors and output, in elements
+    int col0;       // first column handled by this launch
+    int ncols;      // columns handled by this launch
+    float scale;
+    uint32_t fbytes[kMaxIn];  // input factor sizes in bytes (buffer addressing)
+    uint32_t own_bytes;
+};
+
+// Raw buffer resource over [base, base + bytes): word 3 is the gfx9-family
+// default for untyped dword access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// ------------------------------------------------------------ compile-time loops
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Value of lane (group base + J) for every lane of an LPR-lane group.
+template <int LPR, int J>
+__device__ __forceinline__ int group_bcast(int x)
+{
+    if constexpr (LPR == 1) {
+        return x;
+    } else if constexpr (LPR == 64) {
+        return __builtin_amdgcn_readlane(x, J);
+    } else {
+        // ds_swizzle bit mode inside 32-lane halves: lane' = (lane & and) | or
+        constexpr int and_mask = 0x1F & ~(LPR - 1);
+        return __builtin_amdgcn_ds_swizzle(x, and_mask | (J << 5));
+    }
+}
+template <int LPR, int J>
+__device__ __forceinline__ float group_bcast_f(float x)
+{
+    return __int_as_float(group_bcast<LPR, J>(__float_as_int(x)));
+}
+
+// Broadcast of lane (group base + jb*U + JU).  One batch per tile: compile-time
+// ds_swizzle.  Several batches: the batch index is a run-time (wave-uniform)
+// loop counter, so ds_bpermute, or v_readlane when the group is the wave.
+template <int LPR, int U, int NB, int JU>
+__device__ __forceinline__ int tile_bcast(int x, int jb, int lane)
+{
+    if constexpr (NB == 1) {
+        return group_bcast<LPR, JU>(x);
+    } else if constexpr (LPR == 64) {
+        return __builtin_amdgcn_readlane(x, jb * U + JU);
+    } else {
+        return __builtin_amdgcn_ds_bpermute(((lane & ~(LPR - 1)) + jb * U + JU) << 2, x);
+    }
+}
+template <int LPR, int U, int NB, int JU>
+__device__ __forceinline__ float tile_bcast_f(float x, int jb, int lane)
+{
+    return __int_as_float(tile_bcast<LPR, U, NB, JU>(__float_as_int(x), jb, lane));
+}
+
+template <int LPR>
+__device__ __forceinline__ float group_sum(float x)
+{
+#pragma unroll
+    for (int m = 1; m < LPR; m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// ------------------------------------------------------------------ row access
+// Row<T, RPL>: RPL consecutive columns of a factor row as fp32.  `lp` is the
+// lane's base pointer (factor + its first column), `rb` the row stride in
+// bytes (a compile-time constant on the vector path, so the address is one
+// 64-bit shift-add).
+template <typename T, int RPL> struct Row;
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <> struct Row<float, 4> {
+    using Raw = float4;
+    static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+    }
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
+    {
+        return *reinterpret_cast<const float4*>(lp + (uint64_t)row * rb);
+    }
+    static __device__ __forceinline__ Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
+    {
+        v[0] = r.x; v[1] = r.y; v[2] = r.z; v[3] = r.w;
+    }
+};
+
+template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
+    using Raw = uint4;
+    static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
+    {
+        return *reinterpret_cast<const uint4*>(lp + (uint64_t)row * rb);
+    }
+    static __device__ __forceinline__ Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
+    static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[8])
+    {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = __uint_as_float(w[i] << 16);
+            v[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+        }
+    }
+};
+
+template <> struct Row<float, 1> {
+    using Raw = float;
+    static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0.f; }
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
+    {
+        return *reinterpret_cast<const float*>(lp + (uint64_t)row * rb);
+    }
+    static __device__ __forceinline__ Raw zero() { return 0.f; }
+    static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = r; }
+};
+
+template <> struct Row<uint16_t, 1> {
+    using Raw = uint32_t;
+    static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0u; }
+    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
+    {
+        return *reinterpret_cast<const uint16_t*>(lp + (uint64_t)row * rb);
+    }
+    static __device__ __forceinline__ Raw zero() { return 0u; }
+    static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = __uint_as_float(r << 16); }
+};
+
+// Output row pieces: RPL fp32 columns of row `row`, starting at column c.
+template <int RPL>
+__device__ __forceinline__ void store_cols(float* out, int64_t row, int64_t ld, int c, const float (&v)[RPL])
+{
+    float* p = out + row * ld + c;
+    if constexpr (RPL % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < RPL; i += 4)
+            *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) p[i] = v[i];
+    }
+}
+
+template <int RPL>
+__device__ __forceinline__ void atomic_cols(float* out, int64_t row, int64_t ld, int c, const float (&v)[RPL])
+{
+    float* p = out + row * ld + c;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) atomicAdd(p + i, v[i]);
+}
+
+template <int RPL>
+__device__ __forceinline__ void zero_rows(float* out, int64_t first, int64_t last_excl, int64_t ld, int c)
+{
+    float z[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) z[i] = 0.f;
+    for (int64_t r = first; r < last_excl; ++r) store_cols<RPL>(out, r, ld, c, z);
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int pop_chunk(int* queue, int lane)
+{
+    int c = 0;
+    if (lane == 0) c = atomicAdd(queue, 1);
+    return __builtin_amdgcn_readfirstlane(c);
+}
+
+// --------------------------------------------------------------- MTTKRP kernel
+// KIND 0: MTTKRP.  KIND 1: scale * MTTKRP of the residuals val - CP model,
+// recomputed per nonzero from all factor rows.  KIND 2: the sparse CP loss,
+// sum over nonzeros of (val - CP model)^2 (per-entry work in fp32, each
+// squared residual added in fp64 by the group's first lane, one fp64 atomic
+// per wave; no output matrix).  Memory accesses are
+// software-pipelined:
+//  * the nonzero metadata of tile tau+2 is loaded (VGPRs) while tile tau is
+//    processed and parked in a 2-slot LDS ring at the start of tile tau+1, so
+//    its latency is hidden behind at least two batches of work;
+//  * the factor-row gathers of batch q+1 are issued before batch q is
+//    consumed (two register buffers), so a wave always has a batch in flight.
+// A tile is TS >= 2U nonzeros per group, a batch U nonzeros per group.
+template <int NIN, int LPR, int RPL, typename T, int KIND, bool BUF>
+__global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
+{
+    constexpr int G = 64 / LPR;
+    constexpr int RT = LPR * RPL;
+    constexpr int UMAX = (NIN <= 2) ? AMPED_UMAX : (AMPED_UMAX + 1) / 2;
+    constexpr int U = UMAX;                                      // nonzeros per group per batch
+    constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
+    constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
+    constexpr int NB = TS / U;                                   // batches per tile (even)
+    constexpr int NF = NIN + 2;                                  // key, input indices, value
+    constexpr bool VEC = RPL > 1;
+    using RowT = Row<T, RPL>;
+    constexpr bool OWN = KIND >= 1;                              // the output mode's row is read too
+    constexpr bool OUT = KIND != 2;                              // an output matrix is written
+    using OwnRow = Row<float, OWN ? RPL : 1>;
+    static_assert(KIND == 0 || std::is_same<T, float>::value, "residual and loss forms are fp32 only");
+    static_assert(NB % 2 == 0, "batches per tile must be even");
+    static_assert(!BUF || VEC, "buffer addressing is for the vector path");
+
+    __shared__ int s_key[kWaves][2 * G];
+    __shared__ int s_ext[kWaves][2 * G];
+    __shared__ float s_acc[kWaves][2 * G][RT];
+    __shared__ int s_meta[kWaves][2][NF][G * TS];               // [slot][field][group*TS + j]
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane / LPR;
+    const int s = lane % LPR;
+    const bool lane_on = VEC || (s * RPL < p.ncols);
+    const int c = p.col0 + (lane_on ? s * RPL : 0);
+    const int64_t ld = VEC ? (int64_t)RT : p.ld;
+    const uint64_t rb = (uint64_t)ld * sizeof(T);
+    const uint64_t rb_own = (uint64_t)ld * sizeof(float);
+    const float oscale = (KIND == 1) ? p.scale : 1.0f;
+    const char* lbase[NIN];
+#pragma unroll
+    for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(T);
+    const char* obase = OWN ? reinterpret_cast<const char*>(p.own + c) : nullptr;
+    double lsum = 0.0;  // KIND 2: this lane's sum of squared residuals
+    // BUF: every factor is below 4 GiB, so rows are read with buffer loads
+    // addressed by a 32-bit byte offset (row * row_bytes + column bytes)
+    __amdgpu_buffer_rsrc_t rsrc[NIN];
+    __amdgpu_buffer_rsrc_t rsrc_own;
+    const uint32_t cb = (uint32_t)c * (uint32_t)sizeof(T);
+    const uint32_t cb_own = (uint32_t)c * (uint32_t)sizeof(float);
+    if constexpr (BUF) {
+#pragma unroll
+        for (int w = 0; w < NIN; ++w) rsrc[w] = make_rsrc(p.fac[w], p.fbytes[w]);
+        if constexpr (OWN) rsrc_own = make_rsrc(p.own, p.own_bytes);
+    }
+
+    for (;;) {
+        const int chunk = pop_chunk(p.queue, lane);
+        if (chunk >= p.n_chunks) break;
+        const int64_t cs = (int64_t)chunk * p.chunk;
+        const int64_t ce = min(cs + p.chunk, p.nnz);
+        const int64_t Lg = ((ce - cs + G * TS - 1) / (G * TS)) * TS;
+        const int64_t gs = cs + g * Lg;
+        const int64_t ge = min(gs + Lg, ce);
+        const bool gon = gs < ge;
+        const int ntiles = (int)(Lg / TS);
+        const int nbatch = ntiles * NB;
+
+        if (s == 0) {
+            s_key[wv][2 * g] = -1;
+            s_key[wv][2 * g + 1] = -1;
+        }
+        int open_key = -1;
+        bool open_first = true;
+        bool left_shared = false;
+        float acc[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+        if (OUT && gon) {
+            const int first = p.out_idx[gs];
+            const int prev = gs > 0 ? p.out_idx[gs - 1] : -1;
+            left_shared = (prev == first);
+            if (lane_on && first - prev - 1 > 0 && first - prev - 1 < kGapInKernel)
+                zero_rows<RPL>(p.out, prev + 1, first, ld, c);
+            open_key = first;
+        }
+        bool parked = false;
+        auto flush_mid = [&]() {
+            if (open_first && left_shared) {
+                parked = true;
+                float* dst = &s_acc[wv][2 * g][s * RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
+                if (s == 0) {
+                    s_key[wv][2 * g] = open_key;
+                    s_ext[wv][2 * g] = (g == 0) ? 1 : 0;
+                }
+            } else if (lane_on) {
+                float v[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
+                store_cols<RPL>(p.out, open_key, ld, c, v);
+            }
+        };
+
+        // ---- metadata: VGPR staging -> LDS ring.  Lane s of group g holds
+        // nonzeros gs + t*TS + k*4*LPR + 4s .. +3 of each field, read with one
+        // 16-byte load when chunk starts are 4-aligned (the layout arrays are
+        // padded by 4 entries, so such a load never leaves the allocation).
+        const bool vec_meta = (p.chunk & 3) == 0;
+        i32x4 vm[Q4][NF];
+        auto load_meta = [&](int t) {
+#pragma unroll
+            for (int kq = 0; kq < Q4; ++kq) {
+                const int64_t mp = gs + (int64_t)t * TS + kq * 4 * LPR + 4 * s;
+                const bool on = gon && t < ntiles && mp < ge;
+                if (vec_meta) {
+                    const i32x4 z = {0, 0, 0, 0};
+                    vm[kq][0] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.out_idx + mp)) : z;
+#pragma unroll
+                    for (int w = 0; w < NIN; ++w)
+                        vm[kq][1 + w] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.in_idx[w] + mp)) : z;
+                    vm[kq][NF - 1] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.val + mp)) : z;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool one = gon && t < ntiles && mp + e < ge;
+                        vm[kq][0][e] = one ? p.out_idx[mp + e] : 0;
+#pragma unroll
+                        for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = one ? p.in_idx[w][mp + e] : 0;
+                        vm[kq][NF - 1][e] = one ? __float_as_int(p.val[mp + e]) : 0;
+                    }
+                }
+            }
+        };
+        auto park_meta = [&](int slot) {
+#pragma unroll
+            for (int kq = 0; kq < Q4; ++kq)
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    *reinterpret_cast<i32x4*>(&s_meta[wv][slot][f][g * TS + kq * 4 * LPR + 4 * s]) = vm[kq][f];
+            wave_lds_sync();
+        };
+        auto meta_at = [&](int slot, int f, int j) { return s_meta[wv][slot][f][g * TS + j]; };
+
+        typename RowT::Raw rawA[U][NIN], rawB[U][NIN];
+        typename OwnRow::Raw ownA[U], ownB[U];
+
+        // issue the gathers of batch q (idle entries read row 0)
+        auto issue = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U]) {
+            const int t = q / NB;
+            const int j0 = (q % NB) * U;
+            const int slot = t & 1;
+            const int64_t base = gs + (int64_t)t * TS + j0;
+            static_for<U>([&](auto ju) {
+                constexpr int JU = decltype(ju)::value;
+                const bool valid = gon && (base + JU < ge);
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) {
+                    const int ix = valid ? meta_at(slot, 1 + w, j0 + JU) : 0;
+                    if constexpr (BUF) raw[JU][w] = RowT::load_buf(rsrc[w], (uint32_t)ix * (uint32_t)rb + cb);
+                    else if constexpr (VEC) raw[JU][w] = RowT::load(lbase[w], ix, rb);
+                    else raw[JU][w] = lane_on ? RowT::load(lbase[w], ix, rb) : RowT::zero();
+                }
+                if constexpr (OWN) {
+                    const int k = valid ? meta_at(slot, 0, j0 + JU) : 0;
+                    if constexpr (BUF) own[JU] = OwnRow::load_buf(rsrc_own, (uint32_t)k * (uint32_t)rb_own + cb_own);
+                    else if constexpr (VEC) own[JU] = OwnRow::load(obase, k, rb_own);
+                    else own[JU] = lane_on ? OwnRow::load(obase, k, rb_own) : OwnRow::zero();
+                }
+            });
+        };
+
+        // consume batch q from its buffers: Hadamard, scale, running row sum
+        auto consume = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U]) {
+            const int t = q / NB;
+            const int j0 = (q % NB) * U;
+            const int slot = t & 1;
+            const int64_t base = gs + (int64_t)t * TS + j0;
+            static_for<U>([&](auto ju) {
+                constexpr int JU = decltype(ju)::value;
+                const bool valid = gon && (base + JU < ge);
+                const int key = meta_at(slot, 0, j0 + JU);
+                const float val = __int_as_float(meta_at(slot, NF - 1, j0 + JU));
+                float prod[RPL];
+                {
+                    float r0[RPL];
+                    RowT::unpack(raw[JU][0], r0);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) prod[i] = r0[i];
+                }
+#pragma unroll
+                for (int w = 1; w < NIN; ++w) {
+                    float rw[RPL];
+                    RowT::unpack(raw[JU][w], rw);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) prod[i] *= rw[i];
+                }
+                if constexpr (KIND == 2) {
+                    // squared residual of this nonzero, added in fp64
+                    float ow[RPL];
+                    OwnRow::unpack(own[JU], ow);
+                    float part = 0.f;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
+                    const float e = val - group_sum<LPR>(part);
+                    if (valid && s == 0) lsum = fma((double)e, (double)e, lsum);
+                    return;
+                }
+                float coef = val;
+                if constexpr (KIND == 1) {
+                    float ow[RPL];
+                    OwnRow::unpack(own[JU], ow);
+                    float part = 0.f;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
+                    coef = val - group_sum<LPR>(part);
+                }
+                if (valid) {
+                    if (key != open_key) {
+                        flush_mid();
+                        if (lane_on && key - open_key - 1 > 0 && key - open_key - 1 < kGapInKernel)
+                            zero_rows<RPL>(p.out, open_key + 1, key, ld, c);
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+                        open_key = key;
+                        open_first = false;
+                    }
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) acc[i] = fmaf(coef, prod[i], acc[i]);
+                }
+            });
+        };
+
+        if (nbatch > 0) {
+            load_meta(0);
+            park_meta(0);
+            load_meta(1);
+            issue(0, rawA, ownA);
+#pragma unroll 1
+            for (int q = 0; q < nbatch; q += 2) {
+                if ((q % NB) == 0) {
+                    // start of tile t: tile t+1 goes to the ring, tile t+2 is loaded
+                    const int t = q / NB;
+                    park_meta((t + 1) & 1);
+                    load_meta(t + 2);
+                }
+                issue(q + 1, rawB, ownB);
+                consume(q, rawA, ownA);
+                if (q + 2 < nbatch) issue(q + 2, rawA, ownA);
+                consume(q + 1, rawB, ownB);
+            }
+        }
+
+        if constexpr (!OUT) continue;
+
+        // end of the run: the open segment
+        if (gon) {
+            const int nextk = ge < p.nnz ? p.out_idx[ge] : -1;
+            const bool right_shared = (nextk == open_key);
+            if ((open_first && left_shared) || right_shared) {
+                float* dst = &s_acc[wv][2 * g + 1][s * RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
+                if (s == 0) {
+                    s_key[wv][2 * g + 1] = open_key;
+                    s_ext[wv][2 * g + 1] = ((open_first && left_shared && g == 0) ? 1 : 0) |
+                                           ((right_shared && ge == ce) ? 2 : 0);
+                }
+                parked = true;
+            } else if (lane_on) {
+                float v[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
+                store_cols<RPL>(p.out, open_key, ld, c, v);
+            }
+            if (ge == p.nnz && lane_on && p.rows - open_key - 1 > 0 && p.rows - open_key - 1 < kGapInKernel)
+                zero_rows<RPL>(p.out, open_key + 1, p.rows, ld, c);
+        }
+
+        if (__builtin_amdgcn_ballot_w64(parked) != 0) {
+            wave_lds_sync();
+            if (g == 0) {
+                int cur = -1, cur_ext = 0;
+                float cacc[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) cacc[i] = 0.f;
+                auto emit = [&]() {
+                    if (cur < 0 || !lane_on) return;
+                    float v[RPL];
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) v[i] = cacc[i] * oscale;
+                    if (cur_ext) atomic_cols<RPL>(p.out, cur, ld, c, v);
+                    else store_cols<RPL>(p.out, cur, ld, c, v);
+                };
+                for (int qq = 0; qq < 2 * G; ++qq) {
+                    const int k = s_key[wv][qq];
+                    if (k < 0) continue;
+                    const float* src = &s_acc[wv][qq][s * RPL];
+                    if (k != cur) {
+                        emit();
+                        cur = k;
+                        cur_ext = s_ext[wv][qq];
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) cacc[i] = src[i];
+                    } else {
+                        cur_ext |= s_ext[wv][qq];
+#pragma unroll
+                        for (int i = 0; i < RPL; ++i) cacc[i] += src[i];
+                    }
+                }
+                emit();
+            }
+        }
+        wave_lds_sync();
+    }
+    if constexpr (KIND == 2) {
+        // wave sum in fp64, one atomic per wave
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) lsum += __shfl_xor(lsum, m, 64);
+        if (lane == 0 && lsum != 0.0) atomicAdd(p.loss, lsum);
+    }
+}
+
+using KernelFn = void (*)(const KParams);
+
+// Vector instances: fp32 ranks 16/32/64/128 and bf16 ranks 32/64/128 for up
+// to 4 input modes; every other case takes the scalar column-tile path.
+constexpr int kMaxVecNin = 4;
+
+// Kernel pickers, one translation unit each (compiled in parallel).
+KernelFn pick_mttkrp_f32(int nin, int lpr, bool scalar, bool buf);
+KernelFn pick_mttkrp_bf16(int nin, int lpr, bool scalar, bool buf);
+KernelFn pick_grad(int nin, int lpr, bool scalar, bool buf);
+KernelFn pick_loss(int nin, int lpr, bool scalar, bool buf);
+
+}  // namespace dev
+}  // namespace amped
