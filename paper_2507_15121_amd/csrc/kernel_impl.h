@@ -40,11 +40,15 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxIn = kMaxOrder - 1;
 
-// Tuning knobs (compile-time): sub-steps whose gathers are issued together
-// (for up to 2 input modes; half of it above), and the waves per SIMD the
-// register allocation must allow (0 = compiler's choice).
+// Tuning knobs (compile-time): nonzeros per group whose gathers are issued
+// together (MTTKRP with up to 2 input modes; the residual/loss forms and
+// higher orders use the second value), and the waves per SIMD the register
+// allocation must allow (0 = compiler's choice).
 #ifndef AMPED_UMAX
-#define AMPED_UMAX 8
+#define AMPED_UMAX 4
+#endif
+#ifndef AMPED_UMAX_OWN
+#define AMPED_UMAX_OWN 2
 #endif
 #ifndef AMPED_MIN_WAVES
 #define AMPED_MIN_WAVES 0
@@ -278,8 +282,10 @@ __global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KP
 {
     constexpr int G = 64 / LPR;
     constexpr int RT = LPR * RPL;
-    constexpr int UMAX = (NIN <= 2) ? AMPED_UMAX : (AMPED_UMAX + 1) / 2;
-    constexpr int U = UMAX;                                      // nonzeros per group per batch
+    // nonzeros per group per batch: the forms that also read the output
+    // mode's row, and high orders, keep fewer rows in flight per batch
+    constexpr int UMAX = (KIND == 0 && NIN <= 2) ? AMPED_UMAX : AMPED_UMAX_OWN;
+    constexpr int U = UMAX;
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
     constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
     constexpr int NB = TS / U;                                   // batches per tile (even)

@@ -94,3 +94,26 @@ def test_fullsize_bf16_sampled_rows(big):
         e = oracle.rel_fro(got, _oracle_rows(st, f64, d, rows, R))
         log("bf16 mode %d: sampled rel %.2e vs fp64 oracle on fp32 factors" % (d, e))
         assert e <= 1e-2
+
+
+def test_factor_above_4GiB_uses_64bit_gathers():
+    # mode-0 factor: 40M rows x 32 fp32 = 5.1 GB, beyond 32-bit buffer offsets;
+    # modes 1 and 2 gather from it (64-bit addresses), mode 0 does not
+    dims = (40_000_000, 1000, 500)
+    R = 32
+    st = synth.tensor(dims, 2_000_000, "zipf", 1.1, 0.0, seed=12)
+    T = api.Tensor(st.idx, st.val, dims)
+    rng = np.random.default_rng(12)
+    dfac = [torch.empty((d, R), device="cuda").uniform_(-1, 1) for d in dims]
+    f64 = [f.double().cpu().numpy() for f in dfac]
+    for d in range(3):
+        out = torch.full((dims[d], R), float("nan"), device="cuda")
+        api.mttkrp(T, d, [None if w == d else f for w, f in enumerate(dfac)], out=out)
+        torch.cuda.synchronize()
+        rows, _, _ = _sample_rows(st, d, rng, 300)
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        e = oracle.rel_fro(got, _oracle_rows(st, f64, d, rows, R))
+        log("5 GB factor, mode %d: sampled rel %.2e" % (d, e))
+        assert e <= 1e-5
+        assert not torch.isnan(out).any().item()
+    T.close()
