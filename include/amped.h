@@ -56,7 +56,7 @@ typedef enum {
 
 /* Creation options; pass NULL for the defaults. */
 typedef struct {
-    int64_t chunk_nnz;        /* CH: nonzeros per work-queue chunk; 0 = 4096.  Part of
+    int64_t chunk_nnz;        /* CH: nonzeros per work-queue chunk, <= 2^28; 0 = 4096.  Part of
                                  the layout contract (chunk k holds positions
                                  [k*CH, min((k+1)*CH, nnz)) of a mode's order).        */
     int64_t device_byte_cap;  /* 0 = no cap; otherwise creation fails with NOMEM,

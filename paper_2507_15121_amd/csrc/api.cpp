@@ -16,6 +16,7 @@
 
 using amped::HostModeLayout;
 using amped::kMaxOrder;
+using amped::kSinkFloats;
 using amped::ModeDev;
 
 namespace {
@@ -190,8 +191,8 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     bool keep_perm = false;
     if (opts) {
         if (opts->reserved != 0) return fail(AMPED_ERR_INVALID, "options.reserved must be 0");
-        if (opts->chunk_nnz < 0 || opts->chunk_nnz > (1ll << 30))
-            return fail(AMPED_ERR_INVALID, "chunk_nnz %lld outside [0, 2^30]", (long long)opts->chunk_nnz);
+        if (opts->chunk_nnz < 0 || opts->chunk_nnz > amped::kMaxChunk)
+            return fail(AMPED_ERR_INVALID, "chunk_nnz %lld outside [0, 2^28]", (long long)opts->chunk_nnz);
         if (opts->chunk_nnz > 0) chunk = opts->chunk_nnz;
         if (opts->device_byte_cap < 0) return fail(AMPED_ERR_INVALID, "device_byte_cap < 0");
         cap = opts->device_byte_cap;
@@ -225,6 +226,7 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     void* d_vals = nullptr;
     void* d_tmp_perm = nullptr;
     void* d_queues = nullptr;
+    void* d_aux = nullptr;
     try {
         std::vector<int32_t> lex = amped::lex_order(order, dims, nnz, indices);
         HIP_OR_FAIL(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
@@ -239,6 +241,9 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
         if (!keep_perm) HIP_OR_FAIL(t->alloc(&d_tmp_perm, (size_t)nnz * 4), "hipMalloc(perm)");
         HIP_OR_FAIL(t->alloc(&d_queues, (size_t)(order + 1) * sizeof(int)), "hipMalloc(queues)");
         HIP_OR_FAIL(hipMemset(d_queues, 0, (size_t)(order + 1) * sizeof(int)), "hipMemset(queues)");
+        // 16 zero bytes followed by the store sink
+        HIP_OR_FAIL(t->alloc(&d_aux, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMalloc(aux)");
+        HIP_OR_FAIL(hipMemset(d_aux, 0, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMemset(aux)");
 
         for (int d = 0; d < order; ++d) {
             HostModeLayout lay;
@@ -271,11 +276,11 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(values)");
             HIP_OR_FAIL(amped::launch_permute32(p, d_vals, static_cast<int32_t*>(d_perm), nnz, stream), "permute");
             m.val = static_cast<float*>(p);
-            if (!lay.split_rows.empty()) {
-                HIP_OR_FAIL(t->alloc(&p, lay.split_rows.size() * 4), "hipMalloc(split)");
-                HIP_OR_FAIL(hipMemcpy(p, lay.split_rows.data(), lay.split_rows.size() * 4, hipMemcpyHostToDevice),
-                            "hipMemcpy(split)");
-                m.split_rows = static_cast<int32_t*>(p);
+            if (!lay.zero_rows.empty()) {
+                HIP_OR_FAIL(t->alloc(&p, lay.zero_rows.size() * 4), "hipMalloc(zero rows)");
+                HIP_OR_FAIL(hipMemcpy(p, lay.zero_rows.data(), lay.zero_rows.size() * 4, hipMemcpyHostToDevice),
+                            "hipMemcpy(zero rows)");
+                m.zero_rows = static_cast<int32_t*>(p);
             }
             if (!lay.gaps.empty()) {
                 HIP_OR_FAIL(t->alloc(&p, lay.gaps.size() * 4), "hipMalloc(gaps)");
@@ -287,7 +292,9 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             m.chunk = chunk;
             m.n_chunks = t->n_chunks;
             m.rows = dims[d];
-            m.n_split = (int64_t)lay.split_rows.size();
+            m.n_zero = (int64_t)lay.zero_rows.size();
+            m.zero_row = d_aux;
+            m.sink = static_cast<float*>(d_aux) + 4;
             m.n_gaps = (int64_t)lay.gaps.size() / 2;
             m.queue = static_cast<int*>(d_queues) + d;
             t->flags[d] = std::move(lay.flags);

@@ -12,16 +12,20 @@ namespace amped {
 
 constexpr int kMaxOrder = 8;
 constexpr int64_t kDefaultChunk = 4096;
-// Untouched-row runs shorter than this are zeroed inside the MTTKRP kernel by
-// the wave that reaches them; longer runs go to a list zeroed by the init
-// kernel.  Part of the host/kernel contract.
-constexpr int kGapInKernel = 16;
+// Largest chunk: a chunk's metadata arrays stay below 2^30 bytes, so 32-bit
+// buffer offsets into them (with an out-of-range bias) never wrap.
+constexpr int64_t kMaxChunk = int64_t(1) << 28;
+// Scratch floats each tensor keeps for stores that must not land (64 lanes x 8).
+constexpr int kSinkFloats = 512;
+// The init kernel zeroes untouched output rows: runs at least this long as
+// (start, length) ranges, shorter runs row by row from the zero-row list.
+constexpr int kLongGap = 16;
 
 // ----------------------------------------------------------------- host layout
 struct HostModeLayout {
     std::vector<int32_t> perm;        // position -> input nonzero
     std::vector<uint8_t> flags;       // per chunk: bit0 head continues, bit1 tail continues
-    std::vector<int32_t> split_rows;  // output rows shared by two or more chunks
+    std::vector<int32_t> zero_rows;   // rows shared by two or more chunks, then untouched rows of short runs
     std::vector<int32_t> gaps;        // (start, length) pairs of long untouched-row runs
     int64_t touched = 0;              // distinct output indices
 };
@@ -34,7 +38,7 @@ std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, cons
 void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std::vector<int32_t>& base,
                 int mode, std::vector<int32_t>& perm);
 
-// Chunk flags, split rows, long gaps and touched count of a mode order.
+// Chunk flags, zero-row list, long gaps and touched count of a mode order.
 void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
                  HostModeLayout& lay);
 
@@ -47,10 +51,12 @@ struct ModeDev {
     const int32_t* out_idx = nullptr;              // [nnz]
     const int32_t* in_idx[kMaxOrder - 1] = {};     // other modes ascending, each [nnz]
     const float* val = nullptr;                    // [nnz]
-    const int32_t* split_rows = nullptr;           // [n_split]
+    const int32_t* zero_rows = nullptr;            // [n_zero]
     const int32_t* gaps = nullptr;                 // [2 * n_gaps]
-    int64_t nnz = 0, chunk = 0, n_chunks = 0, rows = 0, n_split = 0, n_gaps = 0;
+    int64_t nnz = 0, chunk = 0, n_chunks = 0, rows = 0, n_zero = 0, n_gaps = 0;
     int* queue = nullptr;                          // device work-queue counter
+    const void* zero_row = nullptr;                // 16 zero bytes
+    float* sink = nullptr;                         // kSinkFloats floats of write-only scratch
 };
 
 enum class FactorType { F32 = 0, BF16 = 1 };

@@ -21,8 +21,7 @@
 //    LDS and summed at the end of the chunk; only rows that cross a chunk
 //    boundary are added to memory with fp32 atomics (Sec. 3.2 uses atomics
 //    between SMs), after the init kernel has zeroed them.
-//  * Untouched output rows are zeroed once: short runs by the wave that
-//    reaches them, long runs by the init kernel.
+//  * Untouched output rows are zeroed once, by the init kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,8 +35,14 @@
 namespace amped {
 namespace dev {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlock = 256;  // init and permute kernels
+// MTTKRP kernel block: its waves share nothing, so the block size only sets
+// the granularity of its LDS allocation (compile-time knob)
+#ifndef AMPED_BLOCK
+#define AMPED_BLOCK 256
+#endif
+constexpr int kMttkrpBlock = AMPED_BLOCK;
+constexpr int kWaves = kMttkrpBlock / 64;
 constexpr int kMaxIn = kMaxOrder - 1;
 
 // Tuning knobs (compile-time): nonzeros per group whose gathers are issued
@@ -77,6 +82,8 @@ struct KParams {
     float scale;
     uint32_t fbytes[kMaxIn];  // input factor sizes in bytes (buffer addressing)
     uint32_t own_bytes;
+    const void* zero_row;     // 16 zero bytes: what padding entries read on the 64-bit path
+    float* sink;              // 64 * 8 floats that absorb stores which must not land
 };
 
 // Raw buffer resource over [base, base + bytes): word 3 is the gfx9-family
@@ -147,10 +154,9 @@ __device__ __forceinline__ float group_sum(float x)
 }
 
 // ------------------------------------------------------------------ row access
-// Row<T, RPL>: RPL consecutive columns of a factor row as fp32.  `lp` is the
-// lane's base pointer (factor + its first column), `rb` the row stride in
-// bytes (a compile-time constant on the vector path, so the address is one
-// 64-bit shift-add).
+// Row<T, RPL>: RPL consecutive columns of a factor row as fp32, read from a
+// 64-bit address (load_ptr) or a buffer resource and 32-bit byte offset
+// (load_buf, vector forms only).
 template <typename T, int RPL> struct Row;
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -162,10 +168,7 @@ template <> struct Row<float, 4> {
         const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
         return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     }
-    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
-    {
-        return *reinterpret_cast<const float4*>(lp + (uint64_t)row * rb);
-    }
+    static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const float4*>(a); }
     static __device__ __forceinline__ Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
     {
@@ -180,10 +183,7 @@ template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
         const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
         return make_uint4(v.x, v.y, v.z, v.w);
     }
-    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
-    {
-        return *reinterpret_cast<const uint4*>(lp + (uint64_t)row * rb);
-    }
+    static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint4*>(a); }
     static __device__ __forceinline__ Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[8])
     {
@@ -199,10 +199,7 @@ template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
 template <> struct Row<float, 1> {
     using Raw = float;
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0.f; }
-    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
-    {
-        return *reinterpret_cast<const float*>(lp + (uint64_t)row * rb);
-    }
+    static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const float*>(a); }
     static __device__ __forceinline__ Raw zero() { return 0.f; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = r; }
 };
@@ -210,10 +207,7 @@ template <> struct Row<float, 1> {
 template <> struct Row<uint16_t, 1> {
     using Raw = uint32_t;
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0u; }
-    static __device__ __forceinline__ Raw load(const char* lp, uint32_t row, uint64_t rb)
-    {
-        return *reinterpret_cast<const uint16_t*>(lp + (uint64_t)row * rb);
-    }
+    static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint16_t*>(a); }
     static __device__ __forceinline__ Raw zero() { return 0u; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = __uint_as_float(r << 16); }
 };
@@ -241,13 +235,43 @@ __device__ __forceinline__ void atomic_cols(float* out, int64_t row, int64_t ld,
     for (int i = 0; i < RPL; ++i) atomicAdd(p + i, v[i]);
 }
 
+// RPL fp32 values to a lane's own address (global or LDS).
 template <int RPL>
-__device__ __forceinline__ void zero_rows(float* out, int64_t first, int64_t last_excl, int64_t ld, int c)
+__device__ __forceinline__ void store_vec(float* p, const float (&v)[RPL])
 {
-    float z[RPL];
+    if constexpr (RPL % 4 == 0) {
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) z[i] = 0.f;
-    for (int64_t r = first; r < last_excl; ++r) store_cols<RPL>(out, r, ld, c, z);
+        for (int i = 0; i < RPL; i += 4)
+            *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) p[i] = v[i];
+    }
+}
+template <int RPL>
+__device__ __forceinline__ void lds_store(float* p, const float (&v)[RPL])
+{
+    store_vec<RPL>(p, v);
+}
+
+// U consecutive ints of an LDS ring row (16-byte aligned when U % 4 == 0,
+// 8-byte aligned when U == 2) with the widest reads that fit.
+template <int U>
+__device__ __forceinline__ void lds_vec(const int* p, int (&v)[U])
+{
+    if constexpr (U % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < U; i += 4) {
+            const i32x4 x = *reinterpret_cast<const i32x4*>(p + i);
+            v[i] = x.x; v[i + 1] = x.y; v[i + 2] = x.z; v[i + 3] = x.w;
+        }
+    } else if constexpr (U == 2) {
+        const int2 x = *reinterpret_cast<const int2*>(p);
+        v[0] = x.x; v[1] = x.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < U; ++i) v[i] = p[i];
+    }
 }
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -268,41 +292,50 @@ __device__ __forceinline__ int pop_chunk(int* queue, int lane)
 // KIND 0: MTTKRP.  KIND 1: scale * MTTKRP of the residuals val - CP model,
 // recomputed per nonzero from all factor rows.  KIND 2: the sparse CP loss,
 // sum over nonzeros of (val - CP model)^2 (per-entry work in fp32, each
-// squared residual added in fp64 by the group's first lane, one fp64 atomic
-// per wave; no output matrix).  Memory accesses are
-// software-pipelined:
+// squared residual added in fp64, one fp64 atomic per wave; no output
+// matrix).
+//
+// Memory accesses are software-pipelined:
 //  * the nonzero metadata of tile tau+2 is loaded (VGPRs) while tile tau is
 //    processed and parked in a 2-slot LDS ring at the start of tile tau+1, so
 //    its latency is hidden behind at least two batches of work;
 //  * the factor-row gathers of batch q+1 are issued before batch q is
 //    consumed (two register buffers), so a wave always has a batch in flight.
 // A tile is TS >= 2U nonzeros per group, a batch U nonzeros per group.
+//
+// The inner loop has no per-nonzero bounds test: ring entries past the end of
+// a group's run are padding that carries the run's last output index, a zero
+// value and the row index -1, whose gather returns zeros (past the end of the
+// buffer resource, or redirected to a zero row on the 64-bit path).  Padding
+// therefore adds exact zeros to the open row and never starts a new one.
 template <int NIN, int LPR, int RPL, typename T, int KIND, bool BUF>
-__global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
+__global__ void __launch_bounds__(kMttkrpBlock) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
 {
     constexpr int G = 64 / LPR;
     constexpr int RT = LPR * RPL;
     // nonzeros per group per batch: the forms that also read the output
     // mode's row, and high orders, keep fewer rows in flight per batch
-    constexpr int UMAX = (KIND == 0 && NIN <= 2) ? AMPED_UMAX : AMPED_UMAX_OWN;
-    constexpr int U = UMAX;
+    constexpr int U = (KIND == 0 && NIN <= 2) ? AMPED_UMAX : AMPED_UMAX_OWN;
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
     constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
     constexpr int NB = TS / U;                                   // batches per tile (even)
     constexpr int NF = NIN + 2;                                  // key, input indices, value
+    constexpr int FS = G * TS;                                   // ring entries per field
     constexpr bool VEC = RPL > 1;
     using RowT = Row<T, RPL>;
     constexpr bool OWN = KIND >= 1;                              // the output mode's row is read too
     constexpr bool OUT = KIND != 2;                              // an output matrix is written
     using OwnRow = Row<float, OWN ? RPL : 1>;
+    constexpr int kMetaNT = 2;                                   // non-temporal cache policy
     static_assert(KIND == 0 || std::is_same<T, float>::value, "residual and loss forms are fp32 only");
     static_assert(NB % 2 == 0, "batches per tile must be even");
+    static_assert(TS % 4 == 0 && (U == 1 || U == 2 || U % 4 == 0), "ring rows must be vector aligned");
     static_assert(!BUF || VEC, "buffer addressing is for the vector path");
 
     __shared__ int s_key[kWaves][2 * G];
     __shared__ int s_ext[kWaves][2 * G];
-    __shared__ float s_acc[kWaves][2 * G][RT];
-    __shared__ int s_meta[kWaves][2][NF][G * TS];               // [slot][field][group*TS + j]
+    __shared__ __align__(16) float s_acc[kWaves][2 * G][RT];    // slot 2g+1 is also the in-loop park sink
+    __shared__ __align__(16) int s_meta[kWaves][2][NF][FS];     // [slot][field][group*TS + j]
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -318,7 +351,9 @@ __global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KP
 #pragma unroll
     for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(T);
     const char* obase = OWN ? reinterpret_cast<const char*>(p.own + c) : nullptr;
-    double lsum = 0.0;  // KIND 2: this lane's sum of squared residuals
+    const char* zrow = static_cast<const char*>(p.zero_row);
+    float* const gsink = p.sink + s * RPL;
+    double lsum = 0.0;  // KIND 2: sum of squared residuals (each group's value in all its LPR lanes)
     // BUF: every factor is below 4 GiB, so rows are read with buffer loads
     // addressed by a 32-bit byte offset (row * row_bytes + column bytes)
     __amdgpu_buffer_rsrc_t rsrc[NIN];
@@ -330,183 +365,193 @@ __global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KP
         for (int w = 0; w < NIN; ++w) rsrc[w] = make_rsrc(p.fac[w], p.fbytes[w]);
         if constexpr (OWN) rsrc_own = make_rsrc(p.own, p.own_bytes);
     }
+    // one factor-row gather; row -1 reads zeros
+    auto gather = [&](int w, int ix) -> typename RowT::Raw {
+        if constexpr (BUF) return RowT::load_buf(rsrc[w], (uint32_t)ix * (uint32_t)rb + cb);
+        else return RowT::load_ptr(ix < 0 ? zrow : lbase[w] + (uint64_t)(uint32_t)ix * rb);
+    };
+    auto gather_own = [&](int k) -> typename OwnRow::Raw {
+        if constexpr (BUF) return OwnRow::load_buf(rsrc_own, (uint32_t)k * (uint32_t)rb_own + cb_own);
+        else return OwnRow::load_ptr(k < 0 ? zrow : obase + (uint64_t)(uint32_t)k * rb_own);
+    };
+    const bool vec_meta = (p.chunk & 3) == 0;
 
     for (;;) {
         const int chunk = pop_chunk(p.queue, lane);
         if (chunk >= p.n_chunks) break;
         const int64_t cs = (int64_t)chunk * p.chunk;
-        const int64_t ce = min(cs + p.chunk, p.nnz);
-        const int64_t Lg = ((ce - cs + G * TS - 1) / (G * TS)) * TS;
-        const int64_t gs = cs + g * Lg;
-        const int64_t ge = min(gs + Lg, ce);
-        const bool gon = gs < ge;
-        const int ntiles = (int)(Lg / TS);
+        const int clen = (int)(min(cs + p.chunk, p.nnz) - cs);
+        const int Lg = ((clen + FS - 1) / FS) * TS;            // run length per group, whole tiles
+        const int goff = g * Lg;                                // group's first position in the chunk
+        const int len = max(0, min(Lg, clen - goff));           // nonzeros in the group's run
+        const bool gon = len > 0;
+        const int ntiles = Lg / TS;
         const int nbatch = ntiles * NB;
+        const int64_t gs = cs + goff;
+        const int64_t ge = gs + len;
+        // metadata of this chunk as buffers over [cs, cs + clen rounded up to
+        // 4); reads past that return zeros, so no load needs a bounds branch
+        const uint32_t mbytes = (uint32_t)((clen + 3) & ~3) * 4u;
+        __amdgpu_buffer_rsrc_t mr[NF];
+        mr[0] = make_rsrc(p.out_idx + cs, mbytes);
+#pragma unroll
+        for (int w = 0; w < NIN; ++w) mr[1 + w] = make_rsrc(p.in_idx[w] + cs, mbytes);
+        mr[NF - 1] = make_rsrc(p.val + cs, mbytes);
 
-        if (s == 0) {
-            s_key[wv][2 * g] = -1;
-            s_key[wv][2 * g + 1] = -1;
-        }
-        int open_key = -1;
-        bool open_first = true;
-        bool left_shared = false;
+        int open_key = -1, last_key = -1;
+        int first_open = 1;  // the open row is the run's first
+        int lsh = 0;         // the run's first row continues from the previous position
         float acc[RPL];
 #pragma unroll
         for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
-        if (OUT && gon) {
-            const int first = p.out_idx[gs];
-            const int prev = gs > 0 ? p.out_idx[gs - 1] : -1;
-            left_shared = (prev == first);
-            if (lane_on && first - prev - 1 > 0 && first - prev - 1 < kGapInKernel)
-                zero_rows<RPL>(p.out, prev + 1, first, ld, c);
-            open_key = first;
-        }
-        bool parked = false;
-        auto flush_mid = [&]() {
-            if (open_first && left_shared) {
-                parked = true;
-                float* dst = &s_acc[wv][2 * g][s * RPL];
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
-                if (s == 0) {
-                    s_key[wv][2 * g] = open_key;
-                    s_ext[wv][2 * g] = (g == 0) ? 1 : 0;
-                }
-            } else if (lane_on) {
-                float v[RPL];
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
-                store_cols<RPL>(p.out, open_key, ld, c, v);
+        if constexpr (OUT) {
+            if (gon) {
+                const int first = p.out_idx[gs];
+                const int prev = gs > 0 ? p.out_idx[gs - 1] : -1;
+                last_key = p.out_idx[ge - 1];
+                lsh = (prev == first) ? 1 : 0;
+                open_key = first;
             }
-        };
+            // slot 2g: the run's first row when it continues from the left
+            // (bit 0: from the previous chunk); slot 2g+1: the run's last row
+            if (s == 0) {
+                s_key[wv][2 * g] = lsh ? open_key : -1;
+                s_ext[wv][2 * g] = (g == 0) ? 1 : 0;
+                s_key[wv][2 * g + 1] = -1;
+            }
+        }
 
         // ---- metadata: VGPR staging -> LDS ring.  Lane s of group g holds
         // nonzeros gs + t*TS + k*4*LPR + 4s .. +3 of each field, read with one
-        // 16-byte load when chunk starts are 4-aligned (the layout arrays are
-        // padded by 4 entries, so such a load never leaves the allocation).
-        const bool vec_meta = (p.chunk & 3) == 0;
+        // 16-byte load when chunk starts are 4-aligned.
         i32x4 vm[Q4][NF];
         auto load_meta = [&](int t) {
+            if (t < ntiles) {
 #pragma unroll
-            for (int kq = 0; kq < Q4; ++kq) {
-                const int64_t mp = gs + (int64_t)t * TS + kq * 4 * LPR + 4 * s;
-                const bool on = gon && t < ntiles && mp < ge;
-                if (vec_meta) {
-                    const i32x4 z = {0, 0, 0, 0};
-                    vm[kq][0] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.out_idx + mp)) : z;
+                for (int kq = 0; kq < Q4; ++kq) {
+                    const uint32_t off = (uint32_t)(goff + t * TS + kq * 4 * LPR + 4 * s) * 4u;
+                    if (vec_meta) {
 #pragma unroll
-                    for (int w = 0; w < NIN; ++w)
-                        vm[kq][1 + w] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.in_idx[w] + mp)) : z;
-                    vm[kq][NF - 1] = on ? __builtin_nontemporal_load(reinterpret_cast<const i32x4*>(p.val + mp)) : z;
-                } else {
+                        for (int f = 0; f < NF; ++f) {
+                            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(mr[f], (int)off, 0, kMetaNT);
+                            vm[kq][f] = i32x4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+                        }
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool one = gon && t < ntiles && mp + e < ge;
-                        vm[kq][0][e] = one ? p.out_idx[mp + e] : 0;
+                        for (int f = 0; f < NF; ++f)
 #pragma unroll
-                        for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = one ? p.in_idx[w][mp + e] : 0;
-                        vm[kq][NF - 1][e] = one ? __float_as_int(p.val[mp + e]) : 0;
+                            for (int e = 0; e < 4; ++e)
+                                vm[kq][f][e] = (int)__builtin_amdgcn_raw_buffer_load_b32(mr[f], (int)(off + 4 * e), 0,
+                                                                                         kMetaNT);
                     }
                 }
+            } else {
+#pragma unroll
+                for (int kq = 0; kq < Q4; ++kq)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) vm[kq][f] = i32x4{0, 0, 0, 0};
             }
         };
-        auto park_meta = [&](int slot) {
+        // tile t to ring slot t & 1, entries past the end of the run padded
+        // here (a tile after its loads were issued, so they have landed)
+        auto park_meta = [&](int t) {
 #pragma unroll
-            for (int kq = 0; kq < Q4; ++kq)
+            for (int kq = 0; kq < Q4; ++kq) {
+                const int rel = t * TS + kq * 4 * LPR + 4 * s;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool pad = rel + e >= len;
+                    vm[kq][0][e] = pad ? last_key : vm[kq][0][e];
+#pragma unroll
+                    for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = pad ? -1 : vm[kq][1 + w][e];
+                    vm[kq][NF - 1][e] = pad ? 0 : vm[kq][NF - 1][e];
+                }
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
-                    *reinterpret_cast<i32x4*>(&s_meta[wv][slot][f][g * TS + kq * 4 * LPR + 4 * s]) = vm[kq][f];
+                    *reinterpret_cast<i32x4*>(&s_meta[wv][t & 1][f][g * TS + kq * 4 * LPR + 4 * s]) = vm[kq][f];
+            }
             wave_lds_sync();
         };
-        auto meta_at = [&](int slot, int f, int j) { return s_meta[wv][slot][f][g * TS + j]; };
 
         typename RowT::Raw rawA[U][NIN], rawB[U][NIN];
         typename OwnRow::Raw ownA[U], ownB[U];
 
-        // issue the gathers of batch q (idle entries read row 0)
+        // issue the gathers of batch q
         auto issue = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U]) {
             const int t = q / NB;
             const int j0 = (q % NB) * U;
-            const int slot = t & 1;
-            const int64_t base = gs + (int64_t)t * TS + j0;
-            static_for<U>([&](auto ju) {
-                constexpr int JU = decltype(ju)::value;
-                const bool valid = gon && (base + JU < ge);
+            const int* mrow = &s_meta[wv][t & 1][0][g * TS + j0];
+            int ix[NIN][U];
 #pragma unroll
-                for (int w = 0; w < NIN; ++w) {
-                    const int ix = valid ? meta_at(slot, 1 + w, j0 + JU) : 0;
-                    if constexpr (BUF) raw[JU][w] = RowT::load_buf(rsrc[w], (uint32_t)ix * (uint32_t)rb + cb);
-                    else if constexpr (VEC) raw[JU][w] = RowT::load(lbase[w], ix, rb);
-                    else raw[JU][w] = lane_on ? RowT::load(lbase[w], ix, rb) : RowT::zero();
-                }
-                if constexpr (OWN) {
-                    const int k = valid ? meta_at(slot, 0, j0 + JU) : 0;
-                    if constexpr (BUF) own[JU] = OwnRow::load_buf(rsrc_own, (uint32_t)k * (uint32_t)rb_own + cb_own);
-                    else if constexpr (VEC) own[JU] = OwnRow::load(obase, k, rb_own);
-                    else own[JU] = lane_on ? OwnRow::load(obase, k, rb_own) : OwnRow::zero();
-                }
-            });
+            for (int w = 0; w < NIN; ++w) lds_vec<U>(mrow + (1 + w) * FS, ix[w]);
+            int kk[U];
+            if constexpr (OWN) lds_vec<U>(mrow, kk);
+#pragma unroll
+            for (int ju = 0; ju < U; ++ju) {
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) raw[ju][w] = gather(w, ix[w][ju]);
+                if constexpr (OWN) own[ju] = gather_own(ix[0][ju] < 0 ? -1 : kk[ju]);
+            }
+        };
+
+        // a finished row: stored, or parked in LDS when it is the run's first
+        // row and continues from the left (the store then goes to a sink).
+        // Unneeded parks go to slot 2g+1, which is only filled at the run's end.
+        auto flush = [&]() {
+            const bool pk = (first_open & lsh) != 0;
+            float* lp = &s_acc[wv][2 * g + (pk ? 0 : 1)][s * RPL];
+            lds_store<RPL>(lp, acc);
+            float v[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
+            float* gp = (pk || !lane_on) ? gsink : p.out + (int64_t)open_key * ld + c;
+            store_vec<RPL>(gp, v);
         };
 
         // consume batch q from its buffers: Hadamard, scale, running row sum
         auto consume = [&](int q, typename RowT::Raw (&raw)[U][NIN], typename OwnRow::Raw (&own)[U]) {
             const int t = q / NB;
             const int j0 = (q % NB) * U;
-            const int slot = t & 1;
-            const int64_t base = gs + (int64_t)t * TS + j0;
-            static_for<U>([&](auto ju) {
-                constexpr int JU = decltype(ju)::value;
-                const bool valid = gon && (base + JU < ge);
-                const int key = meta_at(slot, 0, j0 + JU);
-                const float val = __int_as_float(meta_at(slot, NF - 1, j0 + JU));
-                float prod[RPL];
-                {
-                    float r0[RPL];
-                    RowT::unpack(raw[JU][0], r0);
+            const int* mrow = &s_meta[wv][t & 1][0][g * TS + j0];
+            int key[U], vbits[U];
+            if constexpr (OUT) lds_vec<U>(mrow, key);
+            lds_vec<U>(mrow + (NF - 1) * FS, vbits);
 #pragma unroll
-                    for (int i = 0; i < RPL; ++i) prod[i] = r0[i];
-                }
+            for (int ju = 0; ju < U; ++ju) {
+                const float val = __int_as_float(vbits[ju]);
+                float prod[RPL];
+                RowT::unpack(raw[ju][0], prod);
 #pragma unroll
                 for (int w = 1; w < NIN; ++w) {
                     float rw[RPL];
-                    RowT::unpack(raw[JU][w], rw);
+                    RowT::unpack(raw[ju][w], rw);
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) prod[i] *= rw[i];
                 }
-                if constexpr (KIND == 2) {
-                    // squared residual of this nonzero, added in fp64
-                    float ow[RPL];
-                    OwnRow::unpack(own[JU], ow);
-                    float part = 0.f;
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
-                    const float e = val - group_sum<LPR>(part);
-                    if (valid && s == 0) lsum = fma((double)e, (double)e, lsum);
-                    return;
-                }
                 float coef = val;
-                if constexpr (KIND == 1) {
+                if constexpr (OWN) {
                     float ow[RPL];
-                    OwnRow::unpack(own[JU], ow);
+                    OwnRow::unpack(own[ju], ow);
                     float part = 0.f;
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
+                    if constexpr (!VEC) part = lane_on ? part : 0.f;
                     coef = val - group_sum<LPR>(part);
                 }
-                if (valid) {
-                    if (key != open_key) {
-                        flush_mid();
-                        if (lane_on && key - open_key - 1 > 0 && key - open_key - 1 < kGapInKernel)
-                            zero_rows<RPL>(p.out, open_key + 1, key, ld, c);
+                if constexpr (KIND == 2) {
+                    lsum = fma((double)coef, (double)coef, lsum);
+                } else {
+                    if (key[ju] != open_key) {
+                        flush();
 #pragma unroll
                         for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
-                        open_key = key;
-                        open_first = false;
+                        open_key = key[ju];
+                        first_open = 0;
                     }
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) acc[i] = fmaf(coef, prod[i], acc[i]);
                 }
-            });
+            }
         };
 
         if (nbatch > 0) {
@@ -516,43 +561,46 @@ __global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KP
             issue(0, rawA, ownA);
 #pragma unroll 1
             for (int q = 0; q < nbatch; q += 2) {
-                if ((q % NB) == 0) {
-                    // start of tile t: tile t+1 goes to the ring, tile t+2 is loaded
-                    const int t = q / NB;
-                    park_meta((t + 1) & 1);
-                    load_meta(t + 2);
-                }
+                // start of tile t: tile t+1 goes to the ring, tile t+2 is
+                // loaded after the next batch's gathers (loads complete in
+                // order, so consuming batch q then does not wait for it)
+                const bool tile_start = (q % NB) == 0;
+                if (tile_start) park_meta(q / NB + 1);
                 issue(q + 1, rawB, ownB);
+                if (tile_start) load_meta(q / NB + 2);
                 consume(q, rawA, ownA);
-                if (q + 2 < nbatch) issue(q + 2, rawA, ownA);
+                // unconditional, so the wait before the next consume counts
+                // the same loads on every pass; past the last batch the ring
+                // slot holds padding only (its gathers read nothing)
+                issue(q + 2, rawA, ownA);
                 consume(q + 1, rawB, ownB);
             }
         }
 
         if constexpr (!OUT) continue;
 
-        // end of the run: the open segment
+        // end of the run: the open row
+        bool parked = false;
         if (gon) {
             const int nextk = ge < p.nnz ? p.out_idx[ge] : -1;
             const bool right_shared = (nextk == open_key);
-            if ((open_first && left_shared) || right_shared) {
+            const bool left_open = first_open && lsh;  // the run is one row, continued from the left
+            if (left_open && s == 0) s_key[wv][2 * g] = -1;
+            if (left_open || right_shared) {
                 float* dst = &s_acc[wv][2 * g + 1][s * RPL];
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) dst[i] = acc[i];
                 if (s == 0) {
                     s_key[wv][2 * g + 1] = open_key;
-                    s_ext[wv][2 * g + 1] = ((open_first && left_shared && g == 0) ? 1 : 0) |
-                                           ((right_shared && ge == ce) ? 2 : 0);
+                    s_ext[wv][2 * g + 1] = ((left_open && g == 0) ? 1 : 0) | ((right_shared && ge == cs + clen) ? 2 : 0);
                 }
-                parked = true;
             } else if (lane_on) {
                 float v[RPL];
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) v[i] = acc[i] * oscale;
                 store_cols<RPL>(p.out, open_key, ld, c, v);
             }
-            if (ge == p.nnz && lane_on && p.rows - open_key - 1 > 0 && p.rows - open_key - 1 < kGapInKernel)
-                zero_rows<RPL>(p.out, open_key + 1, p.rows, ld, c);
+            parked = lsh || right_shared;
         }
 
         if (__builtin_amdgcn_ballot_w64(parked) != 0) {
@@ -592,9 +640,12 @@ __global__ void __launch_bounds__(kBlock) AMPED_OCCUPANCY mttkrp_kernel(const KP
         wave_lds_sync();
     }
     if constexpr (KIND == 2) {
-        // wave sum in fp64, one atomic per wave
+        // wave sum in fp64, one atomic per wave.  The first log2(LPR) steps add
+        // equal values (every lane of a group holds the group's sum), so they
+        // are exact doublings undone by the final 1/LPR.
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) lsum += __shfl_xor(lsum, m, 64);
+        lsum *= 1.0 / LPR;
         if (lane == 0 && lsum != 0.0) atomicAdd(p.loss, lsum);
     }
 }

@@ -20,8 +20,7 @@
 //    LDS and summed at the end of the chunk; only rows that cross a chunk
 //    boundary are added to memory with fp32 atomics (Sec. 3.2 uses atomics
 //    between SMs), after the init kernel has zeroed them.
-//  * Untouched output rows are zeroed once: short runs by the wave that
-//    reaches them, long runs by the init kernel.
+//  * Untouched output rows are zeroed once, by the init kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,10 +39,12 @@ namespace amped {
 namespace dev {
 
 // ----------------------------------------------------------------- init kernel
-// Resets the work-queue counter (and the loss), zeroes the output rows that
-// several chunks add into, and the long runs of untouched rows.
-__global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, int col0, int ncols,
-                                                      const int32_t* split, int64_t n_split,
+// Resets the work-queue counter (and the loss) and zeroes the output rows
+// the MTTKRP kernel does not store: rows that several chunks add into,
+// untouched rows of short runs (both in the zero-row list) and long runs of
+// untouched rows.  vec4: ld, col0 and ncols are multiples of 4 (16-byte stores).
+__global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, int col0, int ncols, bool vec4,
+                                                      const int32_t* zrows, int64_t n_zero,
                                                       const int32_t* gaps, int64_t n_gaps, int* queue,
                                                       double* loss)
 {
@@ -53,10 +54,13 @@ __global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, in
     }
     if (!out) return;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    const int64_t total = n_split * ncols;
+    const int nv = vec4 ? ncols / 4 : ncols;  // stores per row
+    const int64_t total = n_zero * nv;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += nthreads) {
-        const int64_t r = split[i / ncols];
-        out[r * ld + col0 + (i % ncols)] = 0.f;
+        const int64_t r = zrows[i / nv];
+        const int j = (int)(i % nv);
+        if (vec4) *reinterpret_cast<float4*>(out + r * ld + col0 + 4 * j) = make_float4(0.f, 0.f, 0.f, 0.f);
+        else out[r * ld + col0 + j] = 0.f;
     }
     for (int64_t gi = blockIdx.x; gi < n_gaps; gi += gridDim.x) {
         const int64_t start = gaps[2 * gi], len = gaps[2 * gi + 1];
@@ -64,6 +68,14 @@ __global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, in
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
             out[(start + i / ncols) * ld + col0 + (i % ncols)] = 0.f;
     }
+}
+
+// A factor of `rows` rows is read through a 32-bit buffer offset when one
+// more row still fits: padding entries use row -1, whose offset (2^32 - one
+// row + column bytes) then lies past the end and reads zeros.
+bool fits_buffer(int64_t rows, int rank, int elem_bytes)
+{
+    return (uint64_t)(rows + 1) * (uint64_t)rank * (uint64_t)elem_bytes <= (1ull << 32);
 }
 
 // Vector path: one 16-byte load per lane covers the row (rank * size / 16
@@ -94,7 +106,7 @@ int persistent_grid(KernelFn fn)
     auto it = per_cu.find(reinterpret_cast<const void*>(fn));
     if (it == per_cu.end()) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kMttkrpBlock, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 1;
@@ -106,10 +118,12 @@ int persistent_grid(KernelFn fn)
 hipError_t launch_init(const ModeDev& m, float* out, int64_t ld, int col0, int ncols, double* loss,
                        hipStream_t st)
 {
-    const int64_t work = std::max<int64_t>(m.n_split * ncols, m.n_gaps * kBlock);
-    int grid = (int)std::min<int64_t>(std::max<int64_t>(1, (work + kBlock - 1) / kBlock), 2048);
-    hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(kBlock), 0, st, out, ld, col0, ncols, m.split_rows,
-                       out ? m.n_split : 0, m.gaps, out ? m.n_gaps : 0, m.queue, loss);
+    const bool vec4 = (ld % 4 == 0) && (col0 % 4 == 0) && (ncols % 4 == 0) &&
+                      (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    const int64_t work = std::max<int64_t>(m.n_zero * (vec4 ? ncols / 4 : ncols), m.n_gaps * kBlock);
+    int grid = (int)std::min<int64_t>(std::max<int64_t>(1, (work + kBlock - 1) / kBlock), 4096);
+    hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(kBlock), 0, st, out, ld, col0, ncols, vec4, m.zero_rows,
+                       out ? m.n_zero : 0, m.gaps, out ? m.n_gaps : 0, m.queue, loss);
     return hipGetLastError();
 }
 
@@ -124,6 +138,8 @@ KParams base_params(const ModeDev& m)
     k.chunk = m.chunk;
     k.n_chunks = m.n_chunks;
     k.rows = m.rows;
+    k.zero_row = m.zero_row;
+    k.sink = m.sink;
     return k;
 }
 
@@ -159,11 +175,12 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
     const ModeDev& m = *a.m;
     const int eb = (a.ftype == FactorType::F32) ? 4 : 2;
     const int lpr = vector_lpr(a.rank, eb);
-    // buffer addressing when every factor the kernel reads is below 4 GiB
+    // buffer addressing when every factor the kernel reads fits in 32-bit
+    // offsets with one row to spare
     bool buf = AMPED_BUFFER_LOADS != 0;
     for (int w = 0; w < a.nin; ++w)
-        if ((uint64_t)a.in_rows[w] * (uint64_t)a.rank * (uint64_t)eb >= (1ull << 32)) buf = false;
-    if (a.kind == Kind::ResidualGrad && (uint64_t)m.rows * (uint64_t)a.rank * 4ull >= (1ull << 32)) buf = false;
+        if (!fits_buffer(a.in_rows[w], a.rank, eb)) buf = false;
+    if (a.kind == Kind::ResidualGrad && !fits_buffer(m.rows, a.rank, 4)) buf = false;
     KernelFn fn = lpr ? pick_mttkrp(a.nin, a.ftype, a.kind, lpr, false, buf) : nullptr;
     const bool scalar = (fn == nullptr);
     // the fused residual form needs the whole row in one launch (rank <= 64
@@ -192,7 +209,7 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
         k.col0 = col0;
         k.ncols = ncols;
         void* args[] = {&k};
-        e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kBlock), args, 0, a.stream);
+        e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kMttkrpBlock), args, 0, a.stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -202,9 +219,9 @@ hipError_t launch_cp_loss(const LossArgs& a)
 {
     const ModeDev& m = *a.m;
     const int lpr = vector_lpr(a.rank, 4);
-    bool buf = AMPED_BUFFER_LOADS != 0 && (uint64_t)m.rows * (uint64_t)a.rank * 4ull < (1ull << 32);
+    bool buf = AMPED_BUFFER_LOADS != 0 && fits_buffer(m.rows, a.rank, 4);
     for (int w = 0; w < a.order - 1; ++w)
-        if ((uint64_t)a.in_rows[w] * (uint64_t)a.rank * 4ull >= (1ull << 32)) buf = false;
+        if (!fits_buffer(a.in_rows[w], a.rank, 4)) buf = false;
     KernelFn fn = lpr ? pick_loss(a.order - 1, lpr, false, buf) : nullptr;
     const bool scalar = (fn == nullptr);
     if (scalar && a.rank > 64) return hipErrorNotSupported;
@@ -227,7 +244,7 @@ hipError_t launch_cp_loss(const LossArgs& a)
     const int grid = persistent_grid(fn);
     if (grid <= 0) return hipErrorInvalidDevice;
     void* args[] = {&k};
-    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kBlock), args, 0, a.stream);
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kMttkrpBlock), args, 0, a.stream);
 }
 
 }  // namespace amped

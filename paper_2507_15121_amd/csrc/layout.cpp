@@ -144,16 +144,16 @@ void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode,
         if (e < nnz && key(e - 1) == key(e)) f |= 2;
         lay.flags[k] = f;
     }
-    lay.split_rows.clear();
+    lay.zero_rows.clear();
     for (int64_t k = 1; k < n_chunks; ++k)
         if (lay.flags[k] & 1) {
             const int32_t r = key(k * chunk);
-            if (lay.split_rows.empty() || lay.split_rows.back() != r) lay.split_rows.push_back(r);
+            if (lay.zero_rows.empty() || lay.zero_rows.back() != r) lay.zero_rows.push_back(r);
         }
-    // distinct output indices and long runs of untouched rows
+    // distinct output indices; untouched rows as long runs or single rows
     int nt = omp_get_max_threads();
     if (nt < 1) nt = 1;
-    std::vector<std::vector<int32_t>> tgaps(nt);
+    std::vector<std::vector<int32_t>> tgaps(nt), tlone(nt);
     int64_t touched = 0;
 #pragma omp parallel num_threads(nt) reduction(+ : touched)
     {
@@ -164,25 +164,32 @@ void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode,
             const int64_t prev = (p == 0) ? -1 : key(p - 1);
             if (cur != prev) {
                 touched++;
-                if (cur - prev - 1 >= kGapInKernel) {
+                if (cur - prev - 1 >= kLongGap) {
                     tgaps[t].push_back((int32_t)(prev + 1));
                     tgaps[t].push_back((int32_t)(cur - prev - 1));
+                } else {
+                    for (int64_t r = prev + 1; r < cur; ++r) tlone[t].push_back((int32_t)r);
                 }
             }
         }
     }
     lay.touched = touched;
     lay.gaps.clear();
-    for (int t = 0; t < nt; ++t) lay.gaps.insert(lay.gaps.end(), tgaps[t].begin(), tgaps[t].end());
+    for (int t = 0; t < nt; ++t) {
+        lay.gaps.insert(lay.gaps.end(), tgaps[t].begin(), tgaps[t].end());
+        lay.zero_rows.insert(lay.zero_rows.end(), tlone[t].begin(), tlone[t].end());
+    }
     const int64_t rows = dims[mode];
     if (nnz == 0) {
         lay.gaps.push_back(0);
         lay.gaps.push_back((int32_t)rows);
     } else {
         const int64_t last = key(nnz - 1);
-        if (rows - last - 1 >= kGapInKernel) {
+        if (rows - last - 1 >= kLongGap) {
             lay.gaps.push_back((int32_t)(last + 1));
             lay.gaps.push_back((int32_t)(rows - last - 1));
+        } else {
+            for (int64_t r = last + 1; r < rows; ++r) lay.zero_rows.push_back((int32_t)r);
         }
     }
 }
