@@ -200,10 +200,13 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
         keep_perm = opts->keep_perm == 1;
     }
     // peak device bytes: the N layouts, the kept permutations, and during the
-    // build the raw COO plus one permutation
+    // build the raw COO plus one permutation; per mode at most one int per row
+    // for the zero-row list and long gaps, and the hot-row tables
     const int64_t layout_bytes = (int64_t)order * (order + 1) * 4 * (nnz + 4);
+    int64_t row_bytes = 0;
+    for (int d = 0; d < order; ++d) row_bytes += 4 * dims[d] + 4 * amped::kHotTableLen;
     const int64_t peak = layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
-                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8;
+                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8 + row_bytes + 4096;
     if (cap > 0 && peak > cap)
         return fail(AMPED_ERR_NOMEM, "layouts need up to %lld device bytes, cap is %lld", (long long)peak,
                     (long long)cap);
@@ -282,6 +285,9 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
                             "hipMemcpy(zero rows)");
                 m.zero_rows = static_cast<int32_t*>(p);
             }
+            HIP_OR_FAIL(t->alloc(&p, lay.hot.size() * 4), "hipMalloc(hot rows)");
+            HIP_OR_FAIL(hipMemcpy(p, lay.hot.data(), lay.hot.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(hot rows)");
+            m.hot = static_cast<int32_t*>(p);
             if (!lay.gaps.empty()) {
                 HIP_OR_FAIL(t->alloc(&p, lay.gaps.size() * 4), "hipMalloc(gaps)");
                 HIP_OR_FAIL(hipMemcpy(p, lay.gaps.data(), lay.gaps.size() * 4, hipMemcpyHostToDevice),
@@ -428,6 +434,7 @@ amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const*
     for (int w = 0; w < t->order; ++w)
         if (w != mode) {
             a.in_rows[j] = t->dims[w];
+            a.in_hot[j] = t->mode[w].hot;
             a.in_factors[j++] = factors[w];
         }
     a.own_factor = grad ? static_cast<const float*>(factors[mode]) : nullptr;
@@ -480,6 +487,7 @@ amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* facto
     for (int w = 1; w < t->order; ++w) {
         a.in_factors[w - 1] = factors[w];
         a.in_rows[w - 1] = t->dims[w];
+        a.in_hot[w - 1] = t->mode[w].hot;
     }
     a.loss = loss;
     a.stream = static_cast<hipStream_t>(stream);

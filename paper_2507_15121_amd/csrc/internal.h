@@ -15,6 +15,13 @@ constexpr int64_t kDefaultChunk = 4096;
 // Largest chunk: a chunk's metadata arrays stay below 2^30 bytes, so 32-bit
 // buffer offsets into them (with an out-of-range bias) never wrap.
 constexpr int64_t kMaxChunk = int64_t(1) << 28;
+// Hot-row tables: for every power of two K <= kHotMax, a direct-mapped table
+// of K slots; slot s names the row r with r % K == s that the most nonzeros
+// use in this mode (kHotEmpty if no row maps to s).  The tables of all K are
+// stored back to back, the one for K at offset K - 1.
+constexpr int kHotMax = 1024;
+constexpr int kHotTableLen = 2 * kHotMax - 1;
+constexpr int32_t kHotEmpty = -2;
 // Scratch floats each tensor keeps for stores that must not land (64 lanes x 8).
 constexpr int kSinkFloats = 512;
 // The init kernel zeroes untouched output rows: runs at least this long as
@@ -27,6 +34,7 @@ struct HostModeLayout {
     std::vector<uint8_t> flags;       // per chunk: bit0 head continues, bit1 tail continues
     std::vector<int32_t> zero_rows;   // rows shared by two or more chunks, then untouched rows of short runs
     std::vector<int32_t> gaps;        // (start, length) pairs of long untouched-row runs
+    std::vector<int32_t> hot;         // hot-row tables of this mode's rows [kHotTableLen]
     int64_t touched = 0;              // distinct output indices
 };
 
@@ -38,7 +46,8 @@ std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, cons
 void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std::vector<int32_t>& base,
                 int mode, std::vector<int32_t>& perm);
 
-// Chunk flags, zero-row list, long gaps and touched count of a mode order.
+// Chunk flags, zero-row list, long gaps, hot-row tables and touched count of a
+// mode order.
 void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
                  HostModeLayout& lay);
 
@@ -55,6 +64,7 @@ struct ModeDev {
     const int32_t* gaps = nullptr;                 // [2 * n_gaps]
     int64_t nnz = 0, chunk = 0, n_chunks = 0, rows = 0, n_zero = 0, n_gaps = 0;
     int* queue = nullptr;                          // device work-queue counter
+    const int32_t* hot = nullptr;                  // hot-row tables of this mode [kHotTableLen]
     const void* zero_row = nullptr;                // 16 zero bytes
     float* sink = nullptr;                         // kSinkFloats floats of write-only scratch
 };
@@ -70,6 +80,7 @@ struct LaunchArgs {
     Kind kind = Kind::Mttkrp;
     const void* in_factors[kMaxOrder - 1] = {};    // input-mode factors, modes ascending
     int64_t in_rows[kMaxOrder - 1] = {};           // their row counts
+    const int32_t* in_hot[kMaxOrder - 1] = {};     // their hot-row tables
     const float* own_factor = nullptr;             // factor of the output mode (ResidualGrad)
     float scale = 1.0f;                            // ResidualGrad output scale
     float* out = nullptr;
@@ -90,6 +101,7 @@ struct LossArgs {
     const float* own_factor = nullptr;
     const float* in_factors[kMaxOrder - 1] = {};
     int64_t in_rows[kMaxOrder - 1] = {};
+    const int32_t* in_hot[kMaxOrder - 1] = {};
     double* loss = nullptr;
     hipStream_t stream = nullptr;
 };

@@ -36,13 +36,25 @@ namespace amped {
 namespace dev {
 
 constexpr int kBlock = 256;  // init and permute kernels
-// MTTKRP kernel block: its waves share nothing, so the block size only sets
-// the granularity of its LDS allocation (compile-time knob)
+// MTTKRP kernel blocks: the waves of a block share only the hot-row cache,
+// so MTTKRP (which uses it) runs 512-thread blocks, one per CU beside a large
+// cache, and the residual and loss forms (whose extra own-row registers leave
+// them short of waves otherwise) 256-thread blocks without it.
 #ifndef AMPED_BLOCK
-#define AMPED_BLOCK 256
+#define AMPED_BLOCK 512
 #endif
-constexpr int kMttkrpBlock = AMPED_BLOCK;
-constexpr int kWaves = kMttkrpBlock / 64;
+#ifndef AMPED_BLOCK_OWN
+#define AMPED_BLOCK_OWN 256
+#endif
+__host__ __device__ constexpr int mttkrp_block(int kind) { return kind == 0 ? AMPED_BLOCK : AMPED_BLOCK_OWN; }
+// Output rows are written with non-temporal stores (compile-time knob), and
+// factor-row gathers with this cache policy.
+#ifndef AMPED_OUT_NT
+#define AMPED_OUT_NT 0
+#endif
+#ifndef AMPED_GATHER_AUX
+#define AMPED_GATHER_AUX 0
+#endif
 constexpr int kMaxIn = kMaxOrder - 1;
 
 // Tuning knobs (compile-time): nonzeros per group whose gathers are issued
@@ -65,6 +77,8 @@ constexpr int kMaxIn = kMaxOrder - 1;
 #endif
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct KParams {
     const int32_t* out_idx;
@@ -84,7 +98,18 @@ struct KParams {
     uint32_t own_bytes;
     const void* zero_row;     // 16 zero bytes: what padding entries read on the 64-bit path
     float* sink;              // 64 * 8 floats that absorb stores which must not land
+    const int32_t* hot[kMaxIn];  // per input: direct-mapped table of hot_k rows kept in LDS
+    int hot_k;                // LDS row-cache slots per input (power of two; 0 = none)
 };
+
+// Dynamic LDS of the MTTKRP kernel: 16 zero bytes, then (vector path, K > 0)
+// the tags [NIN][K] and rows [NIN][K][row bytes] of the hot-row cache.
+__host__ __device__ constexpr size_t hot_tag_offset() { return 16; }
+__host__ __device__ constexpr size_t hot_row_offset(int nin, int k) { return (16 + (size_t)nin * k * 4 + 15) & ~(size_t)15; }
+__host__ __device__ constexpr size_t hot_lds_bytes(int nin, int k, int row_bytes)
+{
+    return k > 0 ? hot_row_offset(nin, k) + (size_t)nin * k * row_bytes : 16;
+}
 
 // Raw buffer resource over [base, base + bytes): word 3 is the gfx9-family
 // default for untyped dword access.
@@ -159,13 +184,17 @@ __device__ __forceinline__ float group_sum(float x)
 // (load_buf, vector forms only).
 template <typename T, int RPL> struct Row;
 
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 template <> struct Row<float, 4> {
     using Raw = float4;
+    static __device__ __forceinline__ Raw merge(const Raw& a, const u32x4& b)
+    {
+        return make_float4(__uint_as_float(__float_as_uint(a.x) | b.x), __uint_as_float(__float_as_uint(a.y) | b.y),
+                           __uint_as_float(__float_as_uint(a.z) | b.z), __uint_as_float(__float_as_uint(a.w) | b.w));
+    }
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
     {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AMPED_GATHER_AUX);
         return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const float4*>(a); }
@@ -178,9 +207,13 @@ template <> struct Row<float, 4> {
 
 template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
     using Raw = uint4;
+    static __device__ __forceinline__ Raw merge(const Raw& a, const u32x4& b)
+    {
+        return make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+    }
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
     {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AMPED_GATHER_AUX);
         return make_uint4(v.x, v.y, v.z, v.w);
     }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint4*>(a); }
@@ -214,17 +247,11 @@ template <> struct Row<uint16_t, 1> {
 
 // Output row pieces: RPL fp32 columns of row `row`, starting at column c.
 template <int RPL>
+__device__ __forceinline__ void store_vec(float* p, const float (&v)[RPL]);
+template <int RPL>
 __device__ __forceinline__ void store_cols(float* out, int64_t row, int64_t ld, int c, const float (&v)[RPL])
 {
-    float* p = out + row * ld + c;
-    if constexpr (RPL % 4 == 0) {
-#pragma unroll
-        for (int i = 0; i < RPL; i += 4)
-            *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
-    } else {
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) p[i] = v[i];
-    }
+    store_vec<RPL>(out + row * ld + c, v);
 }
 
 template <int RPL>
@@ -235,9 +262,24 @@ __device__ __forceinline__ void atomic_cols(float* out, int64_t row, int64_t ld,
     for (int i = 0; i < RPL; ++i) atomicAdd(p + i, v[i]);
 }
 
-// RPL fp32 values to a lane's own address (global or LDS).
+// RPL fp32 values of an output row to a lane's own address.
 template <int RPL>
 __device__ __forceinline__ void store_vec(float* p, const float (&v)[RPL])
+{
+    if constexpr (RPL % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < RPL; i += 4) {
+            const f32x4 x = {v[i], v[i + 1], v[i + 2], v[i + 3]};
+            if constexpr (AMPED_OUT_NT != 0) __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p + i));
+            else *reinterpret_cast<f32x4*>(p + i) = x;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) p[i] = v[i];
+    }
+}
+template <int RPL>
+__device__ __forceinline__ void lds_store(float* p, const float (&v)[RPL])
 {
     if constexpr (RPL % 4 == 0) {
 #pragma unroll
@@ -247,11 +289,6 @@ __device__ __forceinline__ void store_vec(float* p, const float (&v)[RPL])
 #pragma unroll
         for (int i = 0; i < RPL; ++i) p[i] = v[i];
     }
-}
-template <int RPL>
-__device__ __forceinline__ void lds_store(float* p, const float (&v)[RPL])
-{
-    store_vec<RPL>(p, v);
 }
 
 // U consecutive ints of an LDS ring row (16-byte aligned when U % 4 == 0,
@@ -309,8 +346,10 @@ __device__ __forceinline__ int pop_chunk(int* queue, int lane)
 // buffer resource, or redirected to a zero row on the 64-bit path).  Padding
 // therefore adds exact zeros to the open row and never starts a new one.
 template <int NIN, int LPR, int RPL, typename T, int KIND, bool BUF>
-__global__ void __launch_bounds__(kMttkrpBlock) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
+__global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_kernel(const KParams p)
 {
+    constexpr int kMttkrpBlock = mttkrp_block(KIND);
+    constexpr int kWaves = kMttkrpBlock / 64;
     constexpr int G = 64 / LPR;
     constexpr int RT = LPR * RPL;
     // nonzeros per group per batch: the forms that also read the output
@@ -365,10 +404,48 @@ __global__ void __launch_bounds__(kMttkrpBlock) AMPED_OCCUPANCY mttkrp_kernel(co
         for (int w = 0; w < NIN; ++w) rsrc[w] = make_rsrc(p.fac[w], p.fbytes[w]);
         if constexpr (OWN) rsrc_own = make_rsrc(p.own, p.own_bytes);
     }
-    // one factor-row gather; row -1 reads zeros
+    // Hot-row cache (vector path): the K rows of each input factor named by
+    // the direct-mapped table p.hot[w] are copied to LDS once per block; ring
+    // entries that name a cached row are rewritten to -2 - slot when parked.
+    extern __shared__ __align__(16) char s_dyn[];
+    constexpr int RB = RT * (int)sizeof(T);  // row bytes on the vector path
+    const int K = (VEC && KIND == 0) ? p.hot_k : 0;
+    const int* const htag = reinterpret_cast<const int*>(s_dyn + hot_tag_offset());
+    const uint32_t hrow = (uint32_t)hot_row_offset(NIN, K);  // byte offset of the cached rows
+    {
+        if (threadIdx.x < 4) reinterpret_cast<int*>(s_dyn)[threadIdx.x] = 0;
+        if constexpr (VEC && KIND == 0) {
+            if (K > 0) {
+                int* tag = reinterpret_cast<int*>(s_dyn + hot_tag_offset());
+#pragma unroll
+                for (int w = 0; w < NIN; ++w) {
+                    for (int i = threadIdx.x; i < K; i += kMttkrpBlock) tag[w * K + i] = p.hot[w][i];
+                    for (int i = threadIdx.x; i < K * LPR; i += kMttkrpBlock) {
+                        const int slot = i / LPR, piece = i % LPR;
+                        const int row = p.hot[w][slot];
+                        u32x4 v = {0u, 0u, 0u, 0u};
+                        if (row >= 0)
+                            v = *reinterpret_cast<const u32x4*>(static_cast<const char*>(p.fac[w]) +
+                                                                 (uint64_t)row * RB + piece * 16);
+                        *reinterpret_cast<u32x4*>(s_dyn + hrow + ((size_t)w * K + slot) * RB + piece * 16) = v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // one factor-row gather: row >= 0 from memory, -1 (padding) zeros, <= -2
+    // cache slot -2 - row from LDS (its memory read then returns zeros: past
+    // the buffer's end, or the zero row on the 64-bit path)
     auto gather = [&](int w, int ix) -> typename RowT::Raw {
-        if constexpr (BUF) return RowT::load_buf(rsrc[w], (uint32_t)ix * (uint32_t)rb + cb);
-        else return RowT::load_ptr(ix < 0 ? zrow : lbase[w] + (uint64_t)(uint32_t)ix * rb);
+        typename RowT::Raw r;
+        if constexpr (BUF) r = RowT::load_buf(rsrc[w], (uint32_t)max(ix, -1) * (uint32_t)rb + cb);
+        else r = RowT::load_ptr(ix < 0 ? zrow : lbase[w] + (uint64_t)(uint32_t)ix * rb);
+        if constexpr (VEC && KIND == 0) {
+            const uint32_t la = ix <= -2 ? hrow + (uint32_t)(w * K + (-2 - ix)) * RB + (uint32_t)s * 16u : 0u;
+            r = RowT::merge(r, *reinterpret_cast<const u32x4*>(s_dyn + la));
+        }
+        return r;
     };
     auto gather_own = [&](int k) -> typename OwnRow::Raw {
         if constexpr (BUF) return OwnRow::load_buf(rsrc_own, (uint32_t)k * (uint32_t)rb_own + cb_own);
@@ -466,6 +543,20 @@ __global__ void __launch_bounds__(kMttkrpBlock) AMPED_OCCUPANCY mttkrp_kernel(co
                     for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = pad ? -1 : vm[kq][1 + w][e];
                     vm[kq][NF - 1][e] = pad ? 0 : vm[kq][NF - 1][e];
                 }
+                if constexpr (VEC && KIND == 0) {
+                    if (K > 0) {
+                        // rows held in the LDS cache become -2 - slot (tags
+                        // are rows or -2, so padding -1 never matches)
+#pragma unroll
+                        for (int w = 0; w < NIN; ++w)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int ix = vm[kq][1 + w][e];
+                                const int slot = ix & (K - 1);
+                                vm[kq][1 + w][e] = (htag[w * K + slot] == ix) ? -2 - slot : ix;
+                            }
+                    }
+                }
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
                     *reinterpret_cast<i32x4*>(&s_meta[wv][t & 1][f][g * TS + kq * 4 * LPR + 4 * s]) = vm[kq][f];
@@ -490,7 +581,7 @@ __global__ void __launch_bounds__(kMttkrpBlock) AMPED_OCCUPANCY mttkrp_kernel(co
             for (int ju = 0; ju < U; ++ju) {
 #pragma unroll
                 for (int w = 0; w < NIN; ++w) raw[ju][w] = gather(w, ix[w][ju]);
-                if constexpr (OWN) own[ju] = gather_own(ix[0][ju] < 0 ? -1 : kk[ju]);
+                if constexpr (OWN) own[ju] = gather_own(ix[0][ju] == -1 ? -1 : kk[ju]);  // -1: padding
             }
         };
 

@@ -24,7 +24,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <unordered_map>
 #include <utility>
@@ -88,31 +91,61 @@ int vector_lpr(int rank, int elem_bytes)
     return lpr;
 }
 
-// Persistent grid size: every CU filled to the kernel's occupancy.
-int persistent_grid(KernelFn fn)
+// Launch shape of an MTTKRP-kernel instance on the current device: the
+// hot-row cache slots K (largest power of two whose LDS, with the kernel's
+// static LDS, fits one block; capped by AMPED_HOT_MAX if set, 0 = no cache),
+// the dynamic LDS bytes and the persistent grid (every CU filled to the
+// occupancy that LDS allows).
+struct Shape {
+    int hot_k = 0;
+    size_t dyn = 16;
+    int grid = 0;
+};
+
+int hot_cap()
+{
+    static const int cap = [] {
+        const char* e = std::getenv("AMPED_HOT_MAX");
+        if (!e || !*e) return kHotMax;
+        const int v = std::atoi(e);
+        return v < 0 ? 0 : std::min(v, kHotMax);
+    }();
+    return cap;
+}
+
+Shape launch_shape(KernelFn fn, int block, int nin, int row_bytes, bool cache)
 {
     static std::mutex mu;
-    static std::unordered_map<const void*, int> per_cu;
-    static std::unordered_map<int, int> cus;
+    static std::map<std::tuple<int, const void*, int, int, bool>, Shape> memo;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Shape sh;
+    if (hipGetDevice(&dev) != hipSuccess) return sh;
+    const void* f = reinterpret_cast<const void*>(fn);
     std::lock_guard<std::mutex> lk(mu);
-    auto cit = cus.find(dev);
-    if (cit == cus.end()) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-        cit = cus.emplace(dev, n).first;
+    const auto key = std::make_tuple(dev, f, nin, row_bytes, cache);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    int cus = 0, max_lds = 0;
+    hipFuncAttributes attr{};
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&attr, f) != hipSuccess)
+        return sh;
+    if (cache) {
+        for (int k = hot_cap(); k >= 16; k >>= 1)
+            if (attr.sharedSizeBytes + hot_lds_bytes(nin, k, row_bytes) <= (size_t)max_lds) {
+                sh.hot_k = k;
+                break;
+            }
     }
-    auto it = per_cu.find(reinterpret_cast<const void*>(fn));
-    if (it == per_cu.end()) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kMttkrpBlock, 0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 1;
-        it = per_cu.emplace(reinterpret_cast<const void*>(fn), nb).first;
-    }
-    return it->second * cit->second;
+    // hot_cap() may not be a power of two: round down
+    while (sh.hot_k & (sh.hot_k - 1)) sh.hot_k &= sh.hot_k - 1;
+    sh.dyn = hot_lds_bytes(nin, sh.hot_k, row_bytes);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, sh.dyn) != hipSuccess || nb < 1) nb = 1;
+    sh.grid = nb * cus;
+    memo.emplace(key, sh);
+    return sh;
 }
 
 hipError_t launch_init(const ModeDev& m, float* out, int64_t ld, int col0, int ncols, double* loss,
@@ -125,6 +158,16 @@ hipError_t launch_init(const ModeDev& m, float* out, int64_t ld, int col0, int n
     hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(kBlock), 0, st, out, ld, col0, ncols, vec4, m.zero_rows,
                        out ? m.n_zero : 0, m.gaps, out ? m.n_gaps : 0, m.queue, loss);
     return hipGetLastError();
+}
+
+// Point the kernel at the K-slot hot tables of its inputs (K = 0: no cache;
+// also when a table is missing).
+void set_hot(KParams& k, int hot_k, const int32_t* const* in_hot, int nin)
+{
+    for (int w = 0; w < nin; ++w)
+        if (!in_hot[w]) hot_k = 0;
+    k.hot_k = hot_k;
+    for (int w = 0; w < nin; ++w) k.hot[w] = hot_k ? in_hot[w] + (hot_k - 1) : nullptr;
 }
 
 KParams base_params(const ModeDev& m)
@@ -198,8 +241,10 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
     k.out = a.out;
     k.ld = a.rank;
     k.scale = a.scale;
-    const int grid = persistent_grid(fn);
-    if (grid <= 0) return hipErrorInvalidDevice;
+    const int block = mttkrp_block(a.kind == Kind::Mttkrp ? 0 : 1);
+    const Shape sh = launch_shape(fn, block, a.nin, a.rank * eb, !scalar && a.kind == Kind::Mttkrp);
+    if (sh.grid <= 0) return hipErrorInvalidDevice;
+    set_hot(k, sh.hot_k, a.in_hot, a.nin);
     const int tile = scalar ? 64 : a.rank;
     for (int col0 = 0; col0 < a.rank; col0 += tile) {
         const int ncols = std::min(tile, a.rank - col0);
@@ -209,7 +254,7 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
         k.col0 = col0;
         k.ncols = ncols;
         void* args[] = {&k};
-        e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kMttkrpBlock), args, 0, a.stream);
+        e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(sh.grid), dim3(block), args, sh.dyn, a.stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -241,10 +286,12 @@ hipError_t launch_cp_loss(const LossArgs& a)
     hipError_t e = launch_init(m, nullptr, 0, 0, 0, a.loss, a.stream);
     if (e != hipSuccess) return e;
     if (m.n_chunks == 0) return hipSuccess;
-    const int grid = persistent_grid(fn);
-    if (grid <= 0) return hipErrorInvalidDevice;
+    const int block = mttkrp_block(2);
+    const Shape sh = launch_shape(fn, block, a.order - 1, a.rank * 4, false);
+    if (sh.grid <= 0) return hipErrorInvalidDevice;
+    set_hot(k, sh.hot_k, a.in_hot, a.order - 1);
     void* args[] = {&k};
-    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kMttkrpBlock), args, 0, a.stream);
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(sh.grid), dim3(block), args, sh.dyn, a.stream);
 }
 
 }  // namespace amped

@@ -92,6 +92,61 @@ void stable_sort_by(const int32_t* idx_w, int64_t dim, std::vector<int32_t>& ord
     radix_sort_pairs(keys, order, bits_for((uint64_t)(dim - 1)));
 }
 
+// Hot-row tables from a sorted key column: the use count of row r is the
+// length of its run.  Runs are split among threads by where they start.
+template <typename Key>
+void hot_tables(int64_t nnz, const Key& key, std::vector<int32_t>& hot)
+{
+    int nt = omp_get_max_threads();
+    if (nt < 1) nt = 1;
+    std::vector<int32_t> brow((size_t)nt * kHotMax, kHotEmpty);
+    std::vector<int64_t> bcnt((size_t)nt * kHotMax, 0);
+#pragma omp parallel num_threads(nt)
+    {
+        const int t = omp_get_thread_num();
+        int32_t* r = &brow[(size_t)t * kHotMax];
+        int64_t* c = &bcnt[(size_t)t * kHotMax];
+        int64_t p = nnz * t / nt;
+        const int64_t hi = nnz * (t + 1) / nt;
+        while (p > 0 && p < hi && key(p - 1) == key(p)) ++p;  // the run belongs to an earlier thread
+        while (p < hi) {
+            const int32_t row = key(p);
+            int64_t e = p + 1;
+            while (e < nnz && key(e) == row) ++e;
+            const int s = row & (kHotMax - 1);
+            if (e - p > c[s] || (e - p == c[s] && row < r[s])) {
+                c[s] = e - p;
+                r[s] = row;
+            }
+            p = e;
+        }
+    }
+    // merge threads, then halve K: slot s of K takes the better of slots s
+    // and s + K of 2K (ties to the smaller row)
+    std::vector<int32_t> row(kHotMax, kHotEmpty);
+    std::vector<int64_t> cnt(kHotMax, 0);
+    for (int t = 0; t < nt; ++t)
+        for (int s = 0; s < kHotMax; ++s) {
+            const int32_t rr = brow[(size_t)t * kHotMax + s];
+            const int64_t cc = bcnt[(size_t)t * kHotMax + s];
+            if (cc > cnt[s] || (cc == cnt[s] && cc > 0 && rr < row[s])) {
+                cnt[s] = cc;
+                row[s] = rr;
+            }
+        }
+    hot.assign(kHotTableLen, kHotEmpty);
+    for (int K = kHotMax;; K >>= 1) {
+        std::copy(row.begin(), row.begin() + K, hot.begin() + (K - 1));
+        if (K == 1) break;
+        const int h = K / 2;
+        for (int s = 0; s < h; ++s)
+            if (cnt[s + h] > cnt[s] || (cnt[s + h] == cnt[s] && cnt[s] > 0 && row[s + h] < row[s])) {
+                cnt[s] = cnt[s + h];
+                row[s] = row[s + h];
+            }
+    }
+}
+
 }  // namespace
 
 std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, const int32_t* idx)
@@ -174,6 +229,7 @@ void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode,
         }
     }
     lay.touched = touched;
+    hot_tables(nnz, key, lay.hot);
     lay.gaps.clear();
     for (int t = 0; t < nt; ++t) {
         lay.gaps.insert(lay.gaps.end(), tgaps[t].begin(), tgaps[t].end());
