@@ -143,6 +143,12 @@ amped_status amped_layout_host(int order, const int64_t *dims, int64_t nnz,
  *
  * Errors (synchronous, nothing enqueued): INVALID for a bad mode/rank, a NULL
  * or misaligned pointer; HIP if a launch fails.
+ *
+ * The most-used rows of each input factor (from the layout's index counts)
+ * are read from an on-chip copy made at launch; results are identical either
+ * way.  The environment variable AMPED_HOT_MAX, read once per process, caps
+ * the rows kept per factor (0 turns the copy off).  Also applies to
+ * amped_mttkrp_bf16.
  */
 amped_status amped_mttkrp(amped_tensor_t t, int mode, int rank, const float *const *factors,
                           float *out, void *stream);

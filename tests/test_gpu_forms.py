@@ -131,3 +131,52 @@ def test_directional_finite_difference():
     log("directional derivative %.6e, central difference %.6e" % (dirderiv, fd))
     assert abs(fd - dirderiv) <= 1e-3 * abs(dirderiv)
     t.close()
+
+
+# ------------------------------------------------------------- hot-row cache
+
+_NO_CACHE_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
+from paper_2507_15121_amd import api, synth
+from gpu_util import dev_factors, hip_mttkrp
+dims = (30000, 4000, 2500)
+st = synth.tensor(dims, 120000, "zipf", 1.3, 0.05, seed=33)
+factors = synth.factors(dims, 32, seed=33)
+t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+out = {}
+for bf in (False, True):
+    dfac = dev_factors(factors, torch.bfloat16 if bf else None)
+    for d in range(3):
+        out["%s%d" % ("b" if bf else "f", d)] = hip_mttkrp(t, d, dfac, bf16=bf)
+np.savez(sys.argv[2], **out)
+"""
+
+
+def test_hot_row_cache_is_bit_exact(tmp_path):
+    """The same launches with the LDS row cache off (AMPED_HOT_MAX=0, read once
+    per process, so in a child process) give bit-identical outputs: cached rows
+    are exact copies and the summation order does not change."""
+    import os
+    import subprocess
+    import sys
+    from gpu_util import hip_mttkrp as hm
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    dims = (30000, 4000, 2500)
+    st = synth.tensor(dims, 120000, "zipf", 1.3, 0.05, seed=33)
+    factors = synth.factors(dims, 32, seed=33)
+    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+    mine = {}
+    for bf in (False, True):
+        dfac = dev_factors(factors, torch.bfloat16 if bf else None)
+        for d in range(3):
+            mine["%s%d" % ("b" if bf else "f", d)] = hm(t, d, dfac, bf16=bf)
+    path = str(tmp_path / "nocache.npz")
+    env = dict(os.environ, AMPED_HOT_MAX="0")
+    log("child run with AMPED_HOT_MAX=0")
+    r = subprocess.run([sys.executable, "-c", _NO_CACHE_CHILD, root, path], env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    other = np.load(path)
+    for k, v in mine.items():
+        np.testing.assert_array_equal(v.view(np.uint32), other[k].view(np.uint32), err_msg=k)
