@@ -104,6 +104,14 @@ struct amped_tensor_s {
 
 namespace {
 
+// Bits needed to hold the values 0..n (0 for n <= 0).
+int bits_for(int64_t n)
+{
+    int b = 0;
+    while (b < 63 && n > 0 && (n >> b)) ++b;
+    return b;
+}
+
 amped_status validate_coo(int order, const int64_t* dims, int64_t nnz, const int32_t* indices, const float* values)
 {
     if (order < 2 || order > kMaxOrder) return fail(AMPED_ERR_INVALID, "order %d outside [2, %d]", order, kMaxOrder);
@@ -205,8 +213,10 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     const int64_t layout_bytes = (int64_t)order * (order + 1) * 4 * (nnz + 4);
     int64_t row_bytes = 0;
     for (int d = 0; d < order; ++d) row_bytes += 4 * dims[d] + 4 * amped::kHotTableLen;
+    // device sort: lexicographic order, key and value ping-pong buffers, scratch
+    const int64_t sort_bytes = 16 * nnz + 4 * amped::sort_scratch_words(nnz);
     const int64_t peak = layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
-                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8 + row_bytes + 4096;
+                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8 + row_bytes + sort_bytes + 4096;
     if (cap > 0 && peak > cap)
         return fail(AMPED_ERR_NOMEM, "layouts need up to %lld device bytes, cap is %lld", (long long)peak,
                     (long long)cap);
@@ -230,8 +240,20 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     void* d_tmp_perm = nullptr;
     void* d_queues = nullptr;
     void* d_aux = nullptr;
+    // device sort buffers (freed at the end of the build)
+    void* d_lex = nullptr;
+    void* d_key_a = nullptr;
+    void* d_key_b = nullptr;
+    void* d_val_b = nullptr;
+    void* d_scratch = nullptr;
     try {
-        std::vector<int32_t> lex = amped::lex_order(order, dims, nnz, indices);
+        // The order of each mode is built on the device: the lexicographic
+        // order (when the input is not already in it) by stable radix sorts
+        // over the modes, last mode first; then per mode a stable radix sort
+        // of that order by i_d, whose sorted keys are the out_idx column.  The
+        // chunk flags and row lists come from those keys on the host.
+        const bool lexi = amped::is_lexicographic(order, nnz, indices);
+        std::vector<int32_t> keys_h((size_t)nnz);
         HIP_OR_FAIL(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
         for (int w = 0; w < order; ++w) {
             HIP_OR_FAIL(t->alloc(&d_cols[w], (size_t)nnz * 4), "hipMalloc(coo)");
@@ -247,19 +269,41 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
         // 16 zero bytes followed by the store sink
         HIP_OR_FAIL(t->alloc(&d_aux, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMalloc(aux)");
         HIP_OR_FAIL(hipMemset(d_aux, 0, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMemset(aux)");
+        HIP_OR_FAIL(t->alloc(&d_key_b, (size_t)nnz * 4), "hipMalloc(sort)");
+        HIP_OR_FAIL(t->alloc(&d_val_b, (size_t)nnz * 4), "hipMalloc(sort)");
+        HIP_OR_FAIL(t->alloc(&d_scratch, (size_t)amped::sort_scratch_words(nnz) * 4), "hipMalloc(sort)");
+        auto sort_pairs = [&](void* keys, void* vals, int64_t dim) -> hipError_t {
+            bool alt = false;
+            hipError_t e = amped::launch_stable_sort_pairs(
+                static_cast<uint32_t*>(keys), static_cast<int32_t*>(vals), static_cast<uint32_t*>(d_key_b),
+                static_cast<int32_t*>(d_val_b), static_cast<uint32_t*>(d_scratch), nnz, bits_for(dim - 1), &alt,
+                stream);
+            if (e != hipSuccess || !alt) return e;
+            e = hipMemcpyAsync(keys, d_key_b, (size_t)nnz * 4, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return e;
+            return hipMemcpyAsync(vals, d_val_b, (size_t)nnz * 4, hipMemcpyDeviceToDevice, stream);
+        };
+        if (!lexi) {
+            HIP_OR_FAIL(t->alloc(&d_lex, (size_t)nnz * 4), "hipMalloc(sort)");
+            HIP_OR_FAIL(t->alloc(&d_key_a, (size_t)nnz * 4), "hipMalloc(sort)");
+            HIP_OR_FAIL(amped::launch_iota(static_cast<int32_t*>(d_lex), nnz, stream), "iota");
+            for (int w = order - 1; w >= 0; --w) {
+                HIP_OR_FAIL(amped::launch_permute32(d_key_a, d_cols[w], static_cast<int32_t*>(d_lex), nnz, stream),
+                            "permute");
+                HIP_OR_FAIL(sort_pairs(d_key_a, d_lex, dims[w]), "radix sort");
+            }
+        }
 
         for (int d = 0; d < order; ++d) {
             HostModeLayout lay;
-            amped::mode_order(dims, nnz, indices, lex, d, lay.perm);
-            amped::mode_tables(dims, nnz, indices, d, chunk, lay);
             void* d_perm = d_tmp_perm;
             if (keep_perm) {
                 HIP_OR_FAIL(t->alloc(&d_perm, (size_t)nnz * 4), "hipMalloc(perm)");
                 t->perm[d] = static_cast<int32_t*>(d_perm);
             }
-            if (nnz)
-                HIP_OR_FAIL(hipMemcpy(d_perm, lay.perm.data(), (size_t)nnz * 4, hipMemcpyHostToDevice),
-                            "hipMemcpy(perm)");
+            if (lexi) HIP_OR_FAIL(amped::launch_iota(static_cast<int32_t*>(d_perm), nnz, stream), "iota");
+            else if (nnz)
+                HIP_OR_FAIL(hipMemcpyAsync(d_perm, d_lex, (size_t)nnz * 4, hipMemcpyDeviceToDevice, stream), "copy");
             ModeDev& m = t->mode[d];
             void* p = nullptr;
             // layout arrays carry 4 padding entries so 16-byte loads of the
@@ -267,7 +311,12 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             const size_t padded = ((size_t)nnz + 4) * 4;
             HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(out_idx)");
             HIP_OR_FAIL(amped::launch_permute32(p, d_cols[d], static_cast<int32_t*>(d_perm), nnz, stream), "permute");
+            // the lexicographic order already is mode 0's order
+            if (d > 0) HIP_OR_FAIL(sort_pairs(p, d_perm, dims[d]), "radix sort");
             m.out_idx = static_cast<int32_t*>(p);
+            if (nnz)
+                HIP_OR_FAIL(hipMemcpyAsync(keys_h.data(), p, (size_t)nnz * 4, hipMemcpyDeviceToHost, stream),
+                            "hipMemcpy(keys)");
             int j = 0;
             for (int w = 0; w < order; ++w) {
                 if (w == d) continue;
@@ -279,6 +328,8 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             HIP_OR_FAIL(t->alloc(&p, nnz ? padded : 0), "hipMalloc(values)");
             HIP_OR_FAIL(amped::launch_permute32(p, d_vals, static_cast<int32_t*>(d_perm), nnz, stream), "permute");
             m.val = static_cast<float*>(p);
+            HIP_OR_FAIL(hipStreamSynchronize(stream), "layout build");
+            amped::mode_tables_sorted(keys_h.data(), nnz, dims[d], chunk, lay);
             if (!lay.zero_rows.empty()) {
                 HIP_OR_FAIL(t->alloc(&p, lay.zero_rows.size() * 4), "hipMalloc(zero rows)");
                 HIP_OR_FAIL(hipMemcpy(p, lay.zero_rows.data(), lay.zero_rows.size() * 4, hipMemcpyHostToDevice),
@@ -305,8 +356,6 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             m.queue = static_cast<int*>(d_queues) + d;
             t->flags[d] = std::move(lay.flags);
             t->touched[d] = lay.touched;
-            // the host permutation is reused by the next mode
-            HIP_OR_FAIL(hipStreamSynchronize(stream), "layout build");
         }
         t->loss_dev = t->mode[0];
         t->loss_dev.queue = static_cast<int*>(d_queues) + order;
@@ -320,9 +369,14 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     }
     t->device_bytes -= (int64_t)nnz * 4;
     t->release(d_vals);
-    if (d_tmp_perm) {
+    for (void* q : {d_tmp_perm, d_lex, d_key_a, d_key_b, d_val_b}) {
+        if (!q) continue;
         t->device_bytes -= (int64_t)nnz * 4;
-        t->release(d_tmp_perm);
+        t->release(q);
+    }
+    if (d_scratch) {
+        t->device_bytes -= amped::sort_scratch_words(nnz) * 4;
+        t->release(d_scratch);
     }
     (void)hipStreamDestroy(stream);
     *out = t;

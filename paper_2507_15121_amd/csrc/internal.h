@@ -51,6 +51,23 @@ void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std:
 void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
                  HostModeLayout& lay);
 
+// The same tables from the mode's sorted output-index column keys[nnz].
+void mode_tables_sorted(const int32_t* keys, int64_t nnz, int64_t rows, int64_t chunk, HostModeLayout& lay);
+
+// True when the COO is already in lexicographic order of (i_0, ..., i_{N-1}).
+bool is_lexicographic(int order, int64_t nnz, const int32_t* idx);
+
+// Device layout build: a stable LSD radix sort of n (key, value) pairs by the
+// low key_bits bits of the keys, 8 bits per pass, ping-ponging between
+// (keys, vals) and (keys_alt, vals_alt); *result_in_alt says where the sorted
+// pairs are.  scratch holds sort_scratch_words(n) 32-bit words.
+int64_t sort_scratch_words(int64_t n);
+hipError_t launch_stable_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                                    uint32_t* scratch, int64_t n, int key_bits, bool* result_in_alt,
+                                    hipStream_t st);
+// a[i] = i for i < n.
+hipError_t launch_iota(int32_t* a, int64_t n, hipStream_t st);
+
 // Gather idx[w][perm[p]] for p in [p0, p1) into dst.
 void gather_i32(const int32_t* src, const int32_t* perm, int64_t p0, int64_t p1, int32_t* dst);
 void gather_f32(const float* src, const int32_t* perm, int64_t p0, int64_t p1, float* dst);

@@ -151,17 +151,7 @@ void hot_tables(int64_t nnz, const Key& key, std::vector<int32_t>& hot)
 
 std::vector<int32_t> lex_order(int order, const int64_t* dims, int64_t nnz, const int32_t* idx)
 {
-    int64_t unsorted = 0;
-#pragma omp parallel for reduction(+ : unsorted) schedule(static)
-    for (int64_t k = 1; k < nnz; ++k) {
-        int cmp = 0;
-        for (int w = 0; w < order && cmp == 0; ++w) {
-            const int32_t a = idx[(int64_t)w * nnz + k - 1], b = idx[(int64_t)w * nnz + k];
-            cmp = (a < b) ? -1 : (a > b) ? 1 : 0;
-        }
-        if (cmp > 0) unsorted++;
-    }
-    if (unsorted == 0) return {};
+    if (is_lexicographic(order, nnz, idx)) return {};
     std::vector<int32_t> perm(nnz);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nnz; ++k) perm[k] = (int32_t)k;
@@ -183,12 +173,13 @@ void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std:
     stable_sort_by(idx + (int64_t)mode * nnz, dims[mode], perm);
 }
 
-void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
-                 HostModeLayout& lay)
+namespace {
+
+// Chunk flags, zero-row list, long gaps, hot-row tables and touched count from
+// key(p), the output index at position p of the mode's order.
+template <typename Key>
+void tables_from_keys(int64_t nnz, int64_t rows, int64_t chunk, const Key& key, HostModeLayout& lay)
 {
-    const int32_t* col = idx + (int64_t)mode * nnz;
-    const int32_t* perm = lay.perm.data();
-    auto key = [&](int64_t p) { return col[perm[p]]; };
     const int64_t n_chunks = (nnz + chunk - 1) / chunk;
     lay.flags.assign(n_chunks, 0);
 #pragma omp parallel for schedule(static)
@@ -235,7 +226,6 @@ void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode,
         lay.gaps.insert(lay.gaps.end(), tgaps[t].begin(), tgaps[t].end());
         lay.zero_rows.insert(lay.zero_rows.end(), tlone[t].begin(), tlone[t].end());
     }
-    const int64_t rows = dims[mode];
     if (nnz == 0) {
         lay.gaps.push_back(0);
         lay.gaps.push_back((int32_t)rows);
@@ -248,6 +238,36 @@ void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode,
             for (int64_t r = last + 1; r < rows; ++r) lay.zero_rows.push_back((int32_t)r);
         }
     }
+}
+
+}  // namespace
+
+void mode_tables(const int64_t* dims, int64_t nnz, const int32_t* idx, int mode, int64_t chunk,
+                 HostModeLayout& lay)
+{
+    const int32_t* col = idx + (int64_t)mode * nnz;
+    const int32_t* perm = lay.perm.data();
+    tables_from_keys(nnz, dims[mode], chunk, [&](int64_t p) { return col[perm[p]]; }, lay);
+}
+
+void mode_tables_sorted(const int32_t* keys, int64_t nnz, int64_t rows, int64_t chunk, HostModeLayout& lay)
+{
+    tables_from_keys(nnz, rows, chunk, [&](int64_t p) { return keys[p]; }, lay);
+}
+
+bool is_lexicographic(int order, int64_t nnz, const int32_t* idx)
+{
+    int64_t unsorted = 0;
+#pragma omp parallel for reduction(+ : unsorted) schedule(static)
+    for (int64_t k = 1; k < nnz; ++k) {
+        int cmp = 0;
+        for (int w = 0; w < order && cmp == 0; ++w) {
+            const int32_t a = idx[(int64_t)w * nnz + k - 1], b = idx[(int64_t)w * nnz + k];
+            cmp = (a < b) ? -1 : (a > b) ? 1 : 0;
+        }
+        if (cmp > 0) unsorted++;
+    }
+    return unsorted == 0;
 }
 
 void gather_i32(const int32_t* src, const int32_t* perm, int64_t p0, int64_t p1, int32_t* dst)

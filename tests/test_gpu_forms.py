@@ -138,25 +138,26 @@ def test_directional_finite_difference():
 _NO_CACHE_CHILD = r"""
 import sys, numpy as np, torch
 sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
-from paper_2507_15121_amd import api, synth
+from paper_2507_15121_amd import api
 from gpu_util import dev_factors, hip_mttkrp
-dims = (30000, 4000, 2500)
-st = synth.tensor(dims, 120000, "zipf", 1.3, 0.05, seed=33)
-factors = synth.factors(dims, 32, seed=33)
-t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+z = np.load(sys.argv[2])
+dims = tuple(int(x) for x in z["dims"])
+factors = [z["f%d" % w] for w in range(3)]
+t = api.Tensor(z["idx"], z["val"], dims, chunk_nnz=256)
 out = {}
 for bf in (False, True):
     dfac = dev_factors(factors, torch.bfloat16 if bf else None)
     for d in range(3):
         out["%s%d" % ("b" if bf else "f", d)] = hip_mttkrp(t, d, dfac, bf16=bf)
-np.savez(sys.argv[2], **out)
+np.savez(sys.argv[3], **out)
 """
 
 
 def test_hot_row_cache_is_bit_exact(tmp_path):
     """The same launches with the LDS row cache off (AMPED_HOT_MAX=0, read once
-    per process, so in a child process) give bit-identical outputs: cached rows
-    are exact copies and the summation order does not change."""
+    per process, so in a child process) give bit-identical outputs.  Values
+    and factors are small integers, so every sum is exact in fp32 and the
+    order in which chunk-boundary atomics land cannot change a bit."""
     import os
     import subprocess
     import sys
@@ -164,17 +165,21 @@ def test_hot_row_cache_is_bit_exact(tmp_path):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     dims = (30000, 4000, 2500)
     st = synth.tensor(dims, 120000, "zipf", 1.3, 0.05, seed=33)
-    factors = synth.factors(dims, 32, seed=33)
-    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+    rng = np.random.default_rng(33)
+    val = rng.integers(1, 5, size=st.nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, size=(d, 32)).astype(np.float32) for d in dims]
+    t = api.Tensor(st.idx, val, dims, chunk_nnz=256)
     mine = {}
     for bf in (False, True):
         dfac = dev_factors(factors, torch.bfloat16 if bf else None)
         for d in range(3):
             mine["%s%d" % ("b" if bf else "f", d)] = hm(t, d, dfac, bf16=bf)
+    inp = str(tmp_path / "inputs.npz")
+    np.savez(inp, dims=np.array(dims), idx=st.idx, val=val, **{"f%d" % w: f for w, f in enumerate(factors)})
     path = str(tmp_path / "nocache.npz")
     env = dict(os.environ, AMPED_HOT_MAX="0")
     log("child run with AMPED_HOT_MAX=0")
-    r = subprocess.run([sys.executable, "-c", _NO_CACHE_CHILD, root, path], env=env, capture_output=True,
+    r = subprocess.run([sys.executable, "-c", _NO_CACHE_CHILD, root, inp, path], env=env, capture_output=True,
                        text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
     other = np.load(path)

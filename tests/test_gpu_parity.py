@@ -179,6 +179,31 @@ def test_device_layout_bit_exact(chunk):
     t.close()
 
 
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_device_layout_wide_keys_matches_host_builder(shuffle):
+    """Index ranges that need 4 radix passes (up to 27 bits), many equal keys
+    and, when shuffled, a device-built lexicographic order: the device layout's
+    permutation and chunk flags equal the host builder's, bit for bit."""
+    dims = (100_000_000, 3, 70_000_000)
+    rng = np.random.default_rng(12)
+    nnz = 300_000
+    idx = np.stack([rng.integers(0, d, nnz) for d in dims]).astype(np.int32)
+    idx[0, : nnz // 3] = 12_345_678          # a long run of one key
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    if not shuffle:
+        o = np.lexsort(idx[::-1])
+        idx, val = idx[:, o], val[o]
+    log("wide keys, shuffled=%s" % shuffle)
+    t = _tensor(idx, val, dims, chunk_nnz=1000, keep_perm=True)
+    for d in range(3):
+        lay = t.layout(d, perm=True)
+        perm, flags = api.layout_host(idx, dims, d, 1000)
+        np.testing.assert_array_equal(lay["perm"], perm)
+        np.testing.assert_array_equal(lay["flags"], flags)
+        np.testing.assert_array_equal(lay["out_idx"], idx[d][perm])
+    t.close()
+
+
 def test_non_default_stream_and_reuse_of_output():
     st = synth.tensor((3000, 2000, 1000), 40000, "zipf", 1.1, 0.0, seed=8)
     factors = synth.factors(st.dims, 32, seed=8)
