@@ -85,9 +85,10 @@ typedef struct {
  *   opts     host, nullable
  *   out      host, receives the handle (set to NULL on failure)
  *
- * The host arrays are only read during the call.  Errors: INVALID for bad
- * arguments, RANGE for an index outside its mode, NOMEM, HIP, UNSUPPORTED
- * (no device).
+ * The orders are computed on the device (stable radix sorts; the same order
+ * amped_layout_host computes on the host).  The host arrays are only read
+ * during the call.  Errors: INVALID for bad arguments, RANGE for an index
+ * outside its mode, NOMEM, HIP, UNSUPPORTED (no device).
  */
 amped_status amped_tensor_create(int order, const int64_t *dims, int64_t nnz,
                                  const int32_t *indices, const float *values,
