@@ -184,6 +184,43 @@ amped_status amped_cp_loss(amped_tensor_t t, int rank, const float *const *facto
 amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float *const *factors,
                            float scale, float *grad, void *stream);
 
+/*
+ * Gram matrix G = A^T A of a dense matrix, the R x R building block of the
+ * CP-ALS update (V = Hadamard product of the other factors' Gram matrices).
+ * Products on the matrix cores in fp32, per-slab partial sums added in fp64
+ * in a fixed order (deterministic).
+ *   A     DEVICE, rows x rank fp32 row-major (rows >= 1, 1 <= rank <= 128)
+ *   G     DEVICE, rank x rank fp64 row-major, overwritten
+ * Stream-ordered temporary memory (hipMallocAsync) holds the partial sums.
+ */
+amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void *stream);
+
+/*
+ * One CP-ALS sweep (CPD by alternating least squares, Sec. 2.1; the mode
+ * loop of Alg. 1 with the standard least-squares update after each MTTKRP):
+ * for d = 0..N-1
+ *   M = MTTKRP_d(factors)                        (amped_mttkrp)
+ *   V = Hadamard over w != d of factors[w]^T factors[w]
+ *   factors[d] = M V^{-1} with unit 2-norm columns; lambda = the column norms
+ *                (a zero column stays zero with lambda 0)
+ * and after the last mode the fit 1 - ||X - Xhat|| / ||X|| of the CP model
+ * Xhat = sum_r lambda_r a_r o b_r o ... to the full tensor (entries not
+ * stored are zeros; exact duplicates add up).  The R x R algebra runs in
+ * fp64 (Cholesky factor of V; a non-positive pivot is replaced by a tiny
+ * one), the row-sized products in fp32.  The fit comes from
+ * ||X||^2 - 2<X, Xhat> + ||Xhat||^2, so with fp32 products its absolute error
+ * is about 1e-6 / (1 - fit), at most about 2e-3 as the fit nears 1.
+ *   factors  host array of `order` DEVICE pointers, each dims[w] x rank fp32,
+ *            16-byte aligned; read, and factors[d] overwritten in mode order
+ *   lambda   DEVICE, rank doubles (16-byte aligned), overwritten
+ *   fit      DEVICE, one double, overwritten
+ * 1 <= rank <= 128.  The tensor keeps a workspace for the rank of its last
+ * sweep (max_d dims[d] x rank floats plus small R x R arrays); sweeps on one
+ * tensor must not overlap.
+ */
+amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float *const *factors, double *lambda,
+                                double *fit, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *amped_last_error(void);
 

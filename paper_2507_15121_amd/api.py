@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "RANGE", 3: "NOMEM", 4: "HIP", 5: "UNS
 # every symbol declared in include/amped.h
 EXPORTED = ["amped_tensor_create", "amped_tensor_destroy", "amped_tensor_info", "amped_tensor_layout",
             "amped_layout_host", "amped_mttkrp", "amped_mttkrp_bf16", "amped_cp_loss", "amped_cp_grad",
-            "amped_last_error", "amped_version"]
+            "amped_gram", "amped_cp_als_sweep", "amped_last_error", "amped_version"]
 
 
 class AmpedError(RuntimeError):
@@ -57,6 +57,8 @@ def lib():
         L.amped_mttkrp_bf16.argtypes = [vp, i32, i32, pvp, vp, vp]
         L.amped_cp_loss.argtypes = [vp, i32, pvp, vp, vp]
         L.amped_cp_grad.argtypes = [vp, i32, i32, pvp, ctypes.c_float, vp, vp]
+        L.amped_gram.argtypes = [vp, i64, i32, vp, vp]
+        L.amped_cp_als_sweep.argtypes = [vp, i32, pvp, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("amped_last_error", "amped_version"):
                 getattr(L, name).restype = ctypes.c_int
@@ -252,3 +254,36 @@ def cp_grad(t: Tensor, mode: int, factors, scale: float, out=None, stream=None):
     _check(lib().amped_cp_grad(t.handle, int(mode), rank, ptrs, ctypes.c_float(scale),
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def gram(A, out=None, stream=None):
+    """A^T A (float64, rank x rank) of a contiguous 2-D float32 device tensor."""
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float32 or A.dim() != 2 \
+            or not A.is_contiguous():
+        raise ValueError("A must be a contiguous 2-D float32 CUDA/HIP tensor")
+    rank = int(A.shape[1])
+    if out is None:
+        out = torch.empty((rank, rank), dtype=torch.float64, device=A.device)
+    if out.dtype != torch.float64 or tuple(out.shape) != (rank, rank) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (rank, rank) float64 tensor")
+    _check(lib().amped_gram(ctypes.c_void_p(A.data_ptr()), int(A.shape[0]), rank, ctypes.c_void_p(out.data_ptr()),
+                            _stream_ptr(stream)))
+    return out
+
+
+def cp_als_sweep(t: Tensor, factors, lam=None, fit=None, stream=None):
+    """One CP-ALS sweep over all modes; factors (float32 device tensors) are
+    updated in place.  Returns (lambda, fit) as float64 device tensors."""
+    torch = _torch()
+    ptrs, rank = _ptr_array(t, factors, torch.float32, None)
+    dev = factors[0].device
+    if lam is None:
+        lam = torch.empty(rank, dtype=torch.float64, device=dev)
+    if fit is None:
+        fit = torch.empty((), dtype=torch.float64, device=dev)
+    if lam.dtype != torch.float64 or lam.numel() != rank or fit.dtype != torch.float64 or fit.numel() != 1:
+        raise ValueError("lambda must hold rank float64 values and fit one float64")
+    _check(lib().amped_cp_als_sweep(t.handle, rank, ptrs, ctypes.c_void_p(lam.data_ptr()),
+                                    ctypes.c_void_p(fit.data_ptr()), _stream_ptr(stream)))
+    return lam, fit

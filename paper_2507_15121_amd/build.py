@@ -23,7 +23,8 @@ ARCH = "gfx950"
 LIB = os.path.join(HERE, "libamped.so")
 SYNTH_LIB = os.path.join(HERE, "libamped_synth.so")
 
-HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_loss.hip", "sort.hip"]
+HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_loss.hip", "sort.hip",
+               "als.hip"]
 HOST_SOURCES = ["api.cpp", "layout.cpp"]
 
 HIPCC_FLAGS = [

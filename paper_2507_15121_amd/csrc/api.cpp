@@ -74,6 +74,18 @@ struct amped_tensor_s {
     int32_t* perm[kMaxOrder] = {};
     std::vector<uint8_t> flags[kMaxOrder];
     int64_t touched[kMaxOrder] = {};
+    // CP-ALS workspace, allocated by the first sweep of a rank
+    struct AlsWork {
+        int rank = 0;
+        float* M = nullptr;        // MTTKRP output, max_d I_d x R
+        double* G = nullptr;       // [N][R][R] Gram matrices
+        double* S = nullptr;       // R x R, M^T M
+        float* partial = nullptr;  // Gram partials
+        double* scratch = nullptr; // 4 R x R
+        float* W = nullptr;        // R x R
+        double* xnorm2 = nullptr;  // ||X||^2 (computed once)
+        bool have_xnorm2 = false;
+    } als;
 
     hipError_t alloc(void** p, size_t bytes)
     {
@@ -524,6 +536,95 @@ amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float* co
     g_err.clear();
     return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), grad, stream,
                       amped::FactorType::F32, amped::Kind::ResidualGrad, scale);
+}
+
+amped_status amped_gram(const float* A, int64_t rows, int rank, double* G, void* stream)
+{
+    g_err.clear();
+    if (!A || !G) return fail(AMPED_ERR_INVALID, "A or G is NULL");
+    if (rows < 1) return fail(AMPED_ERR_INVALID, "rows %lld < 1", (long long)rows);
+    if (rank < 1 || rank > 128) return fail(AMPED_ERR_INVALID, "rank %d outside [1, 128]", rank);
+    int dev = 0;
+    amped_status st = check_device(&dev);
+    if (st != AMPED_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)amped::gram_slabs(rows) * rank * rank * sizeof(float);
+    void* partial = nullptr;
+    hipError_t e = hipMallocAsync(&partial, bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(gram partials)");
+    e = amped::launch_gram(A, rows, rank, static_cast<float*>(partial), G, s);
+    hipError_t e2 = hipFreeAsync(partial, s);
+    if (e != hipSuccess) return hip_fail(e, "amped_gram");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync(gram partials)");
+    return AMPED_OK;
+}
+
+amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factors, double* lambda, double* fit,
+                                void* stream)
+{
+    g_err.clear();
+    amped_status st = check_call(t, 0, rank, reinterpret_cast<const void* const*>(factors), lambda, true, "lambda");
+    if (st != AMPED_OK) return st;
+    if (rank > 128) return fail(AMPED_ERR_INVALID, "rank %d above 128 (CP-ALS)", rank);
+    if (!fit) return fail(AMPED_ERR_INVALID, "fit is NULL");
+    DeviceGuard guard(t->device);
+    if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto& w = t->als;
+    const int N = t->order;
+    hipError_t e = hipSuccess;
+    const size_t RR = (size_t)rank * rank;
+    if (w.rank != rank) {
+        for (void* q : {(void*)w.M, (void*)w.G, (void*)w.S, (void*)w.partial, (void*)w.scratch, (void*)w.W})
+            if (q) t->release(q);
+        double* keep_x = w.xnorm2;
+        const bool keep_have = w.have_xnorm2;
+        w = amped_tensor_s::AlsWork{};
+        w.xnorm2 = keep_x;
+        w.have_xnorm2 = keep_have;
+        int64_t maxrows = 0;
+        for (int d = 0; d < N; ++d) maxrows = std::max(maxrows, t->dims[d]);
+        void* p = nullptr;
+        if ((e = t->alloc(&p, (size_t)maxrows * rank * sizeof(float))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.M = static_cast<float*>(p);
+        if ((e = t->alloc(&p, N * RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.G = static_cast<double*>(p);
+        if ((e = t->alloc(&p, RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.S = static_cast<double*>(p);
+        if ((e = t->alloc(&p, (size_t)amped::gram_slabs(maxrows) * RR * sizeof(float))) != hipSuccess)
+            return hip_fail(e, "als workspace");
+        w.partial = static_cast<float*>(p);
+        if ((e = t->alloc(&p, 4 * RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.scratch = static_cast<double*>(p);
+        if ((e = t->alloc(&p, RR * sizeof(float))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.W = static_cast<float*>(p);
+        if (!w.xnorm2) {
+            if ((e = t->alloc(&p, sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
+            w.xnorm2 = static_cast<double*>(p);
+        }
+        w.rank = rank;
+    }
+    if (!w.have_xnorm2) {
+        if ((e = amped::launch_tensor_norm2(t->mode[0], N - 1, w.xnorm2, s)) != hipSuccess)
+            return hip_fail(e, "tensor norm");
+        w.have_xnorm2 = true;
+    }
+    for (int m = 0; m < N; ++m)
+        if ((e = amped::launch_gram(factors[m], t->dims[m], rank, w.partial, w.G + m * RR, s)) != hipSuccess)
+            return hip_fail(e, "gram");
+    for (int d = 0; d < N; ++d) {
+        st = run_mttkrp(t, d, rank, reinterpret_cast<const void* const*>(factors), w.M, stream,
+                        amped::FactorType::F32, amped::Kind::Mttkrp, 1.0f);
+        if (st != AMPED_OK) return st;
+        if ((e = amped::launch_gram(w.M, t->dims[d], rank, w.partial, w.S, s)) != hipSuccess)
+            return hip_fail(e, "gram");
+        if ((e = amped::launch_als_small(w.G, w.S, N, d, rank, w.scratch, w.W, lambda, d == N - 1, w.xnorm2, fit,
+                                         s)) != hipSuccess)
+            return hip_fail(e, "als update");
+        if ((e = amped::launch_als_solve(w.M, w.W, factors[d], t->dims[d], rank, s)) != hipSuccess)
+            return hip_fail(e, "als solve");
+    }
+    return AMPED_OK;
 }
 
 amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* factors, double* loss, void* stream)

@@ -124,6 +124,19 @@ struct LossArgs {
 };
 hipError_t launch_cp_loss(const LossArgs& a);
 
+// CP-ALS building blocks (csrc/als.hip).  G = A^T A (fp64) of a rows x R fp32
+// matrix, R <= 128, via gram_slabs(rows) x R x R fp32 partials.
+int64_t gram_slabs(int64_t rows);
+hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st);
+// The R x R algebra of the mode-d update (scratch: 4 R x R doubles); G is
+// [N][R][R] and G[d] is replaced by the Gram matrix of the new factor.
+hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, float* W,
+                            double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st);
+// A = M W (rows x R, W R x R), fp32.
+hipError_t launch_als_solve(const float* M, const float* W, float* A, int64_t rows, int R, hipStream_t st);
+// ||X||^2 over a layout whose exact duplicates are adjacent.
+hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, hipStream_t st);
+
 // dst[p] = src[perm[p]] for p < n, 32-bit words, on the device.
 hipError_t launch_permute32(void* dst, const void* src, const int32_t* perm, int64_t n, hipStream_t st);
 

@@ -1,0 +1,145 @@
+"""GPU checks of the CP-ALS building blocks through the C ABI against the
+oracle (oracle/als.py): the Gram matrix on the matrix cores and whole sweeps.
+
+Tolerances.  The MTTKRP and Gram matrices are fp32 products with errors of
+about 1e-6 relative (fp32 rounding over sums the oracle does in fp64); the
+R x R algebra is fp64.  The update A_d = M V^{-1} amplifies relative errors
+of M and V by at most cond(V), which is O(1) for the well-spread random
+factors used here, so factors and lambda are compared at 1e-4 relative
+(Frobenius).  The fit, 1 - sqrt(||X||^2 - 2<X, Xhat> + ||Xhat||^2) / ||X||,
+carries an absolute error of about e / (2 (1 - fit)) for a relative error e
+of about 2e-6 in <X, Xhat>: 1e-5 absolute for the fits below 0.9 tested
+against the oracle, and at most sqrt(2 e) = 2e-3 as the fit nears 1."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import als
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2507_15121_amd import api, synth  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("rows,rank", [(1, 5), (7, 16), (4097, 32), (100_003, 32), (20_000, 48), (9_000, 64),
+                                       (30_001, 100), (5_000, 128)])
+def test_gram_vs_oracle(rows, rank):
+    rng = np.random.default_rng(rows + rank)
+    A = rng.uniform(-1, 1, (rows, rank)).astype(np.float32)
+    G = api.gram(_dev(A)).cpu().numpy()
+    ref = als.gram(A)
+    e = oracle.rel_fro(G, ref)
+    log("gram rows=%d R=%d rel %.2e" % (rows, rank, e))
+    assert e <= 1e-6
+    np.testing.assert_array_equal(G, G.T)
+
+
+def _sweep_pair(idx, val, dims, rank, seed, sweeps=1, chunk=0):
+    rng = np.random.default_rng(seed)
+    F0 = [rng.uniform(-1, 1, (d, rank)).astype(np.float32) for d in dims]
+    t = api.Tensor(idx, val, dims, chunk_nnz=chunk)
+    dF = [_dev(f) for f in F0]
+    Fo = [f.astype(np.float64) for f in F0]
+    out = []
+    for s in range(sweeps):
+        lam, fit = api.cp_als_sweep(t, dF)
+        torch.cuda.synchronize()
+        Fo, lo, fo = als.cp_als_sweep(idx, val, dims, Fo)
+        out.append(([f.cpu().numpy() for f in dF], lam.cpu().numpy(), float(fit.item()), Fo, lo, fo))
+        # continue both from their own iterates (each step is compared above)
+    t.close()
+    return out
+
+
+@pytest.mark.parametrize("rank", [8, 16, 32])
+def test_one_sweep_vs_oracle(rank):
+    dims = (3000, 2000, 1500)
+    st = synth.tensor(dims, 60000, "zipf", 1.1, 0.05, seed=40 + rank)
+    (F, lam, fit, Fo, lo, fo), = _sweep_pair(st.idx, st.val, dims, rank, seed=rank)
+    errs = [oracle.rel_fro(F[d], Fo[d]) for d in range(3)]
+    log("ALS R=%d factor errs %s lambda %.2e fit %.6f vs %.6f" %
+        (rank, ["%.1e" % e for e in errs], oracle.rel_fro(lam, lo), fit, fo))
+    assert max(errs) <= 1e-4
+    assert oracle.rel_fro(lam, lo) <= 1e-4
+    assert abs(fit - fo) <= 1e-5
+
+
+def test_sweeps_track_oracle_and_fit_rises():
+    """A sparse sample of an exact rank-4 model plus 1% noise: 8 sweeps from a
+    random start, each compared with the oracle's sweep from the same start."""
+    dims = (800, 600, 500)
+    rng = np.random.default_rng(50)
+    U = [rng.uniform(0.1, 1.0, (d, 4)) for d in dims]
+    lin = rng.choice(dims[0] * dims[1] * dims[2], size=40000, replace=False)
+    idx = np.array(np.unravel_index(lin, dims), dtype=np.int32)
+    val = np.sum(U[0][idx[0]] * U[1][idx[1]] * U[2][idx[2]], axis=1)
+    val = (val * (1 + 0.01 * rng.standard_normal(val.size))).astype(np.float32)
+    t = api.Tensor(idx, val, dims)
+    F0 = [rng.uniform(-1, 1, (d, 4)).astype(np.float32) for d in dims]
+    dF = [_dev(f) for f in F0]
+    fits = []
+    for s in range(8):
+        start = [f.cpu().numpy().astype(np.float64) for f in dF]
+        lam, fit = api.cp_als_sweep(t, dF)
+        Fo, lo, fo = als.cp_als_sweep(idx, val, dims, start)
+        f = float(fit.item())
+        log("sweep %d fit %.6f oracle %.6f" % (s, f, fo))
+        assert abs(f - fo) <= 1e-5
+        for d in range(3):
+            assert oracle.rel_fro(dF[d].cpu().numpy(), Fo[d]) <= 1e-4
+        fits.append(f)
+    assert all(b >= a - 1e-6 for a, b in zip(fits, fits[1:]))
+    t.close()
+
+
+def test_exact_factors_are_a_fixed_point():
+    """From the exact factors of a fully stored rank-4 tensor, one sweep
+    reproduces the tensor (checked on the reconstruction, 1e-5 relative).  The
+    reported fit comes from ||X||^2 - 2<X, Xhat> + ||Xhat||^2, which cancels
+    as the fit nears 1: an error e of about 2e-6 relative in <X, Xhat> (fp32
+    MTTKRP and Gram products) leaves a fit error of at most sqrt(2 e) = 2e-3."""
+    dims = (40, 30, 20)
+    rng = np.random.default_rng(60)
+    U = [rng.uniform(-1, 1, (d, 4)) for d in dims]
+    X = np.einsum("ir,jr,kr->ijk", U[0], U[1], U[2])
+    idx = np.array(np.unravel_index(np.arange(X.size), dims), dtype=np.int32)
+    val = X.ravel().astype(np.float32)
+    t = api.Tensor(idx, val, dims)
+    dF = [_dev(u) for u in U]
+    lam, fit = api.cp_als_sweep(t, dF)
+    F = [f.cpu().numpy().astype(np.float64) for f in dF]
+    Xhat = np.einsum("r,ir,jr,kr->ijk", lam.cpu().numpy(), F[0], F[1], F[2])
+    e = oracle.rel_fro(Xhat, X)
+    log("fixed point: reconstruction rel %.2e, fit %.8f" % (e, fit.item()))
+    assert e <= 1e-5
+    assert fit.item() >= 1 - 2e-3
+    t.close()
+
+
+def test_duplicates_add_up_in_the_fit():
+    dims = (500, 400, 300)
+    st = synth.tensor(dims, 20000, "zipf", 1.1, 0.0, seed=70)
+    idx = np.concatenate([st.idx, st.idx[:, :3000]], axis=1)        # 3000 exact duplicates
+    val = np.concatenate([st.val, st.val[:3000] * 0.5])
+    (F, lam, fit, Fo, lo, fo), = _sweep_pair(idx, val, dims, 8, seed=7, chunk=512)
+    log("duplicates: fit %.6f oracle %.6f" % (fit, fo))
+    assert abs(fit - fo) <= 1e-5
+    assert max(oracle.rel_fro(F[d], Fo[d]) for d in range(3)) <= 1e-4
+
+
+def test_order_four():
+    dims = (600, 500, 400, 50)
+    st = synth.tensor(dims, 30000, "zipf", 1.2, 0.0, seed=80)
+    (F, lam, fit, Fo, lo, fo), = _sweep_pair(st.idx, st.val, dims, 16, seed=8)
+    errs = [oracle.rel_fro(F[d], Fo[d]) for d in range(4)]
+    log("order 4: errs %s fit %.6f vs %.6f" % (["%.1e" % e for e in errs], fit, fo))
+    assert max(errs) <= 1e-4 and abs(fit - fo) <= 1e-5
