@@ -218,6 +218,39 @@ def main():
         forms["cp_loss_and_grad"] = {"ms_per_step": ms_cp, "loss": float(loss),
                                      "nnz_per_s": (N + 1) * st.nnz / (ms_cp * 1e-3)}
         log("cp loss+grad: %s" % forms["cp_loss_and_grad"])
+        if R <= 128:
+            # CP-ALS sweeps (MTTKRP + Gram + R x R algebra + update per mode)
+            # on copies of the factors, and the Gram kernel on its own
+            als_fac = [f.clone() for f in dfac]
+            lam = torch.empty(R, dtype=torch.float64, device="cuda")
+            fitv = torch.empty((), dtype=torch.float64, device="cuda")
+            api.cp_als_sweep(T, als_fac, lam, fitv, stream=stream)
+            torch.cuda.synchronize()
+            n_sw = max(1, min(args.steps, 5))
+            a.record(stream)
+            for _ in range(n_sw):
+                api.cp_als_sweep(T, als_fac, lam, fitv, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms_als = a.elapsed_time(b) / n_sw
+            big = max(range(N), key=lambda d: st.dims[d])
+            G = torch.empty((R, R), dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                api.gram(dfac[big], out=G, stream=stream)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(10):
+                api.gram(dfac[big], out=G, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms_gram = a.elapsed_time(b) / 10
+            rows = st.dims[big]
+            forms["cp_als_sweep"] = {"ms_per_sweep": ms_als, "fit_after": float(fitv), "sweeps": n_sw + 1,
+                                     "gram_ms": ms_gram, "gram_rows": rows,
+                                     "gram_TFLOPs": 2.0 * rows * R * R / (ms_gram * 1e-3) / 1e12,
+                                     "gram_GBps": rows * R * 4 / (ms_gram * 1e-3) / 1e9}
+            log("cp-als sweep: %s" % forms["cp_als_sweep"])
+            del als_fac
 
     if args.copy_calibration:
         n = 1 << 30  # 4 GiB of fp32 read, 4 GiB written

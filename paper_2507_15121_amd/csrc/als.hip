@@ -47,74 +47,117 @@ __device__ __forceinline__ float pick(const float (&x)[T], int t)
     return r;
 }
 
-// T = number of 32-column tiles (R <= 32 T).  Grid (slabs, tile groups), one
-// wave per block.
+// T = number of 32-column tiles (R <= 32 T).  Grid (slabs, tile groups);
+// four waves per block each take a quarter of the slab's rows and keep up to
+// kGramMaxPairs 32x32 tiles in MFMA accumulators, with kGramBatch row pairs of
+// loads in flight before their MFMAs.  The four waves' tiles are then summed
+// through LDS in wave order (deterministic) into the slab's partial.
+constexpr int kGramBatch = 8;
 template <int T>
-__global__ void __launch_bounds__(64) gram_partial(const float* A, int64_t rows, int R, int64_t slab_rows,
-                                                   float* partial)
+__global__ void __launch_bounds__(256) gram_partial(const float* A, int64_t rows, int R, int64_t slab_rows,
+                                                    float* partial)
 {
     constexpr int NP = T * T;
-    const int lane = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * slab_rows;
-    const int64_t r1 = std::min<int64_t>(r0 + slab_rows, rows);
+    constexpr int NPB = NP < kGramMaxPairs ? NP : kGramMaxPairs;   // tiles per block
+    constexpr int B = T <= 2 ? kGramBatch : kGramBatch / 2;          // row pairs per load batch
+    __shared__ float s_t[4][NPB][32 * 32];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b0 = (int64_t)blockIdx.x * slab_rows;
+    const int64_t b1 = std::min<int64_t>(b0 + slab_rows, rows);
+    const int64_t q = ((slab_rows + 3) / 4 + 1) & ~(int64_t)1;   // even rows per wave, 4 q >= slab_rows
+    const int64_t r0 = std::min<int64_t>(b0 + wave * q, b1);
+    const int64_t r1 = std::min<int64_t>(r0 + q, b1);
     const int p0 = blockIdx.y * kGramMaxPairs;
     const int np = std::min(kGramMaxPairs, NP - p0);
-    f32x16 acc[kGramMaxPairs];
+    f32x16 acc[NPB];
 #pragma unroll
-    for (int q = 0; q < kGramMaxPairs; ++q)
+    for (int j = 0; j < NPB; ++j)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+        for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
     const int col = lane & 31;
     const int kk = lane >> 5;
-    for (int64_t i = r0; i < r1; i += 2) {
-        const int64_t row = i + kk;
-        const bool rv = row < r1;
-        float x[T];
+    // batches of B row pairs, double-buffered: batch k+1 is loaded while
+    // batch k feeds the MFMAs
+    auto load = [&](float (&x)[B][T], int64_t i) {
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int c = t * 32 + col;
-            x[t] = (rv && c < R) ? A[row * R + c] : 0.f;
-        }
+        for (int u = 0; u < B; ++u) {
+            const int64_t row = i + 2 * u + kk;
+            const bool rv = row < r1;
 #pragma unroll
-        for (int q = 0; q < kGramMaxPairs; ++q) {
-            if (q < np) {
-                const int p = p0 + q;
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick<T>(x, p / T), pick<T>(x, p % T), acc[q], 0, 0,
-                                                              0);
+            for (int t = 0; t < T; ++t) {
+                const int c = t * 32 + col;
+                x[u][t] = (rv && c < R) ? A[row * R + c] : 0.f;
             }
         }
+    };
+    auto fma_batch = [&](const float (&x)[B][T]) {
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+#pragma unroll
+            for (int j = 0; j < NPB; ++j) {
+                if (j < np) {
+                    const int p = p0 + j;
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick<T>(x[u], p / T), pick<T>(x[u], p % T), acc[j],
+                                                                  0, 0, 0);
+                }
+            }
+    };
+    float xa[B][T], xb[B][T];
+    if (r0 < r1) load(xa, r0);
+    for (int64_t i = r0; i < r1; i += 4 * B) {
+        load(xb, i + 2 * B);      // rows past r1 read as zeros
+        fma_batch(xa);
+        if (i + 4 * B < r1) load(xa, i + 4 * B);
+        fma_batch(xb);
     }
     // lane l holds output column l%32; value v sits in row 8(v/4) + 4(l/32) + v%4
+#pragma unroll
+    for (int j = 0; j < NPB; ++j) {
+        if (j >= np) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) s_t[wave][j][(8 * (v >> 2) + 4 * kk + (v & 3)) * 32 + col] = acc[j][v];
+    }
+    __syncthreads();
     float* out = partial + (int64_t)blockIdx.x * R * R;
-#pragma unroll
-    for (int q = 0; q < kGramMaxPairs; ++q) {
-        if (q >= np) continue;
-        const int p = p0 + q;
-        const int tm = p / T, tn = p % T;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int m = 8 * (v >> 2) + 4 * kk + (v & 3);
-            const int r = tm * 32 + m, c = tn * 32 + col;
-            if (r < R && c < R) out[r * R + c] = acc[q][v];
-        }
+    for (int e = threadIdx.x; e < np * 1024; e += 256) {
+        const int j = e >> 10, m = (e >> 5) & 31, n = e & 31;
+        const float sum = ((s_t[0][j][e & 1023] + s_t[1][j][e & 1023]) + s_t[2][j][e & 1023]) + s_t[3][j][e & 1023];
+        const int p = p0 + j;
+        const int r = (p / T) * 32 + m, c = (p % T) * 32 + n;
+        if (r < R && c < R) out[r * R + c] = sum;
     }
 }
 
+// G[e] = sum over slabs of partial[slab][e] in fp64.  A block takes 32
+// consecutive entries; its 8 slab lanes add every 8th slab, then the 8 sums
+// are added in lane order (deterministic).
 __global__ void __launch_bounds__(256) gram_reduce(const float* partial, int64_t nslab, int R, double* G)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= R * R) return;
-    double s = 0.0;
-    for (int64_t k = 0; k < nslab; ++k) s += (double)partial[k * R * R + e];
-    G[e] = s;
+    __shared__ double s[8][32];
+    const int e32 = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + e32;
+    const int RR = R * R;
+    double acc = 0.0;
+    if (e < RR)
+        for (int64_t k = sl; k < nslab; k += 8) acc += (double)partial[k * RR + e];
+    s[sl][e32] = acc;
+    __syncthreads();
+    if (sl == 0 && e < RR) {
+        double t = 0.0;
+        for (int j = 0; j < 8; ++j) t += s[j][e32];
+        G[e] = t;
+    }
 }
 
-// R x R fp64 algebra of one mode update, one block of 256 threads.
-// scratch: 4 R x R doubles.  G: [N][R][R] (G[d] is replaced).
+// R x R fp64 algebra of one mode update, one block of 256 threads.  Works
+// in 4 R x R doubles: LDS when they fit (dynamic, in_lds), else the global
+// scratch.  G: [N][R][R] (G[d] is replaced).
 __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int N, int d, int R, double* scratch,
                                                  float* W, double* lambda, int last, const double* xnorm2,
-                                                 double* fit)
+                                                 double* fit, int in_lds)
 {
+    extern __shared__ __align__(16) double s_small[];
+    if (in_lds) scratch = s_small;
     const int tid = threadIdx.x;
     const int RR = R * R;
     double* V = scratch;
@@ -164,11 +207,13 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
         }
     }
     __syncthreads();
-    // T = S V^{-1}
+    // S into V's slot (V is no longer needed), then T = S V^{-1}
+    for (int e = tid; e < RR; e += 256) V[e] = S[e];
+    __syncthreads();
     for (int e = tid; e < RR; e += 256) {
         const int i = e / R, j = e % R;
         double s = 0.0;
-        for (int k = 0; k < R; ++k) s += S[i * R + k] * Vi[k * R + j];
+        for (int k = 0; k < R; ++k) s += V[i * R + k] * Vi[k * R + j];
         T[e] = s;
     }
     __syncthreads();
@@ -192,43 +237,97 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
         W[e] = lj > 0.0 ? (float)(Vi[e] / lj) : 0.f;
     }
     __syncthreads();
-    if (last && tid == 0) {
+    if (last) {
         // <X, Xhat> = sum_r lambda_r (S W)_rr = trace(S V^{-1}) over columns
-        // with lambda_r > 0; ||Xhat||^2 = lambda^T (Hadamard of all G) lambda
-        double inner = 0.0;
-        for (int r = 0; r < R; ++r)
-            if (lambda[r] > 0.0) inner += T[r * R + r];
+        // with lambda_r > 0; ||Xhat||^2 = lambda^T (Hadamard of all G) lambda.
+        // Per-thread sums over a fixed slice, then a fixed-order block sum.
+        __shared__ double part[256];
         double xh = 0.0;
-        for (int i = 0; i < R; ++i)
-            for (int j = 0; j < R; ++j) {
-                double h = 1.0;
-                for (int w = 0; w < N; ++w) h *= G[(int64_t)w * RR + i * R + j];
-                xh += lambda[i] * lambda[j] * h;
-            }
-        const double x2 = *xnorm2;
-        const double res = x2 - 2.0 * inner + xh;
-        *fit = x2 > 0.0 ? 1.0 - sqrt(res > 0.0 ? res : 0.0) / sqrt(x2) : 0.0;
+        for (int e = tid; e < RR; e += 256) {
+            const int i = e / R, j = e % R;
+            double h = 1.0;
+            for (int w = 0; w < N; ++w) h *= G[(int64_t)w * RR + e];
+            xh += lambda[i] * lambda[j] * h;
+        }
+        part[tid] = xh;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (tid < off) part[tid] += part[tid + off];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double inner = 0.0;
+            for (int r = 0; r < R; ++r)
+                if (lambda[r] > 0.0) inner += T[r * R + r];
+            const double x2 = *xnorm2;
+            const double res = x2 - 2.0 * inner + part[0];
+            *fit = x2 > 0.0 ? 1.0 - sqrt(res > 0.0 ? res : 0.0) / sqrt(x2) : 0.0;
+        }
     }
 }
 
-// A = M W for rows x R fp32 matrices (row-major), W R x R; 64 rows per block.
-constexpr int kSolveRows = 64;
-__global__ void __launch_bounds__(256) als_solve(const float* M, const float* W, float* A, int64_t rows, int R)
+// A = M W for rows x R fp32 matrices (row-major), W R x R.  A block of 256
+// threads stages RB rows of M (row stride R + 1 in LDS, so the rows a wave
+// reads fall in different banks) and W; thread (g, c8) computes rows
+// 4g .. 4g+3 and columns 8 c8 .. 8 c8 + 7 from registers.
+__global__ void __launch_bounds__(256) als_solve(const float* M, const float* W, float* A, int64_t rows, int R,
+                                                 int RB)
 {
-    extern __shared__ float s_solve[];
-    float* sW = s_solve;             // [R][R]
-    float* sM = s_solve + R * R;     // [kSolveRows][R]
+    extern __shared__ __align__(16) float s_solve[];
+    const int C8 = (R + 7) / 8;                 // column groups of 8
+    const int RW = 8 * C8;                      // padded row length of W
+    float* sW = s_solve;                        // [R][RW]
+    float* sM = s_solve + R * RW;               // [RB][R + 1]
     const int tid = threadIdx.x;
-    for (int e = tid; e < R * R; e += 256) sW[e] = W[e];
-    const int64_t r0 = (int64_t)blockIdx.x * kSolveRows;
-    const int nr = (int)std::min<int64_t>(kSolveRows, rows - r0);
-    for (int e = tid; e < nr * R; e += 256) sM[e] = M[r0 * R + e];
+    for (int e = tid; e < R * RW; e += 256) {
+        const int k = e / RW, c = e % RW;
+        sW[e] = c < R ? W[k * R + c] : 0.f;
+    }
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int nr = (int)std::min<int64_t>(RB, rows - r0);
+    if ((R & 3) == 0) {
+        const float4* M4 = reinterpret_cast<const float4*>(M + r0 * R);
+        for (int e = tid; e < nr * R / 4; e += 256) {
+            const float4 v = M4[e];
+            const int i = (4 * e) / R, k = (4 * e) % R;
+            float* d = &sM[i * (R + 1) + k];
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    } else {
+        for (int e = tid; e < nr * R; e += 256) sM[(e / R) * (R + 1) + e % R] = M[r0 * R + e];
+    }
     __syncthreads();
-    for (int e = tid; e < nr * R; e += 256) {
-        const int i = e / R, c = e % R;
-        float s = 0.f;
-        for (int k = 0; k < R; ++k) s = fmaf(sM[i * R + k], sW[k * R + c], s);
-        A[r0 * R + e] = s;
+    const int g = tid / C8, c8 = tid % C8;
+    const int i0 = 4 * g;
+    if (i0 >= nr) return;
+    float acc[4][8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[j][c] = 0.f;
+    for (int k = 0; k < R; ++k) {
+        const float4 w0 = *reinterpret_cast<const float4*>(&sW[k * RW + 8 * c8]);
+        const float4 w1 = *reinterpret_cast<const float4*>(&sW[k * RW + 8 * c8 + 4]);
+        const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float m = (i0 + j < nr) ? sM[(i0 + j) * (R + 1) + k] : 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[j][c] = fmaf(m, w[c], acc[j][c]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j >= nr) continue;
+        float* out = A + (r0 + i0 + j) * R + 8 * c8;
+        if ((R & 7) == 0) {   // 32-byte aligned run of 8 columns
+            *reinterpret_cast<float4*>(out) = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+            *reinterpret_cast<float4*>(out + 4) = make_float4(acc[j][4], acc[j][5], acc[j][6], acc[j][7]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (8 * c8 + c < R) out[c] = acc[j][c];
+        }
     }
 }
 
@@ -265,7 +364,7 @@ __global__ void __launch_bounds__(256) tensor_norm2(const int32_t* out_idx, InId
 
 int64_t gram_slabs(int64_t rows)
 {
-    return std::max<int64_t>(1, std::min<int64_t>((rows + 4095) / 4096, 2048));
+    return std::max<int64_t>(1, std::min<int64_t>((rows + 8191) / 8192, 2048));
 }
 
 hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st)
@@ -278,29 +377,32 @@ hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, doub
     const int groups = (T * T + kGramMaxPairs - 1) / kGramMaxPairs;
     dim3 grid((unsigned)nslab, (unsigned)groups);
     switch (T) {
-    case 1: hipLaunchKernelGGL(gram_partial<1>, grid, dim3(64), 0, st, A, rows, R, slab_rows, partial); break;
-    case 2: hipLaunchKernelGGL(gram_partial<2>, grid, dim3(64), 0, st, A, rows, R, slab_rows, partial); break;
-    case 3: hipLaunchKernelGGL(gram_partial<3>, grid, dim3(64), 0, st, A, rows, R, slab_rows, partial); break;
-    default: hipLaunchKernelGGL(gram_partial<4>, grid, dim3(64), 0, st, A, rows, R, slab_rows, partial); break;
+    case 1: hipLaunchKernelGGL(gram_partial<1>, grid, dim3(256), 0, st, A, rows, R, slab_rows, partial); break;
+    case 2: hipLaunchKernelGGL(gram_partial<2>, grid, dim3(256), 0, st, A, rows, R, slab_rows, partial); break;
+    case 3: hipLaunchKernelGGL(gram_partial<3>, grid, dim3(256), 0, st, A, rows, R, slab_rows, partial); break;
+    default: hipLaunchKernelGGL(gram_partial<4>, grid, dim3(256), 0, st, A, rows, R, slab_rows, partial); break;
     }
-    hipLaunchKernelGGL(gram_reduce, dim3((R * R + 255) / 256), dim3(256), 0, st, partial, nslab, R, G);
+    hipLaunchKernelGGL(gram_reduce, dim3((R * R + 31) / 32), dim3(256), 0, st, partial, nslab, R, G);
     return hipGetLastError();
 }
 
 hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, float* W,
                             double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st)
 {
-    hipLaunchKernelGGL(als_small, dim3(1), dim3(256), 0, st, G, S, N, d, R, scratch, W, lambda, last ? 1 : 0,
-                       xnorm2, fit);
+    const size_t bytes = (size_t)4 * R * R * sizeof(double);
+    const bool in_lds = bytes <= (size_t)128 * 1024;
+    hipLaunchKernelGGL(als_small, dim3(1), dim3(256), in_lds ? bytes : 0, st, G, S, N, d, R, scratch, W, lambda,
+                       last ? 1 : 0, xnorm2, fit, in_lds ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_als_solve(const float* M, const float* W, float* A, int64_t rows, int R, hipStream_t st)
 {
     if (rows <= 0) return hipSuccess;
-    const size_t lds = (size_t)(R * R + kSolveRows * R) * sizeof(float);
-    hipLaunchKernelGGL(als_solve, dim3((unsigned)((rows + kSolveRows - 1) / kSolveRows)), dim3(256), lds, st, M, W, A,
-                       rows, R);
+    const int C8 = (R + 7) / 8;
+    const int RB = 4 * (256 / C8);     // rows per block: every thread owns 4 rows x 8 columns
+    const size_t lds = (size_t)(R * 8 * C8 + RB * (R + 1)) * sizeof(float);
+    hipLaunchKernelGGL(als_solve, dim3((unsigned)((rows + RB - 1) / RB)), dim3(256), lds, st, M, W, A, rows, R, RB);
     return hipGetLastError();
 }
 
