@@ -60,8 +60,11 @@ def _sweep_pair(idx, val, dims, rank, seed, sweeps=1, chunk=0):
     return out
 
 
-@pytest.mark.parametrize("rank", [8, 16, 32])
+@pytest.mark.parametrize("rank", [8, 16, 32, 5, 12, 100, 128])
 def test_one_sweep_vs_oracle(rank):
+    """R = 8/16/32: vector paths; 5 and 12: scalar solve loads and stores;
+    100: four-tile Gram groups; 128: the R x R algebra in global memory (its
+    4 R^2 doubles exceed the LDS it may use)."""
     dims = (3000, 2000, 1500)
     st = synth.tensor(dims, 60000, "zipf", 1.1, 0.05, seed=40 + rank)
     (F, lam, fit, Fo, lo, fo), = _sweep_pair(st.idx, st.val, dims, rank, seed=rank)
