@@ -4,6 +4,12 @@
 namespace amped {
 namespace dev {
 
+// Rows of up to 64 bytes (rank <= 32) use 8 bytes per lane, so a wave still
+// covers 8 rows per gather at rank 32 (16-byte lanes would make 16 narrow
+// groups); longer rows use 16 bytes per lane.  lpr counts 16-byte lanes.
+#ifndef AMPED_BF16_NARROW
+#define AMPED_BF16_NARROW 1
+#endif
 template <int NIN, typename T, int KIND, bool BUF>
 KernelFn pick_vec(int lpr)
 {
@@ -11,6 +17,13 @@ KernelFn pick_vec(int lpr)
     if constexpr (NIN > kMaxVecNin) {
         return nullptr;
     } else {
+        if (AMPED_BF16_NARROW && lpr <= 4) {
+            switch (lpr) {
+            case 2: return mttkrp_kernel<NIN, 4, 4, T, KIND, BUF>;
+            case 4: return mttkrp_kernel<NIN, 8, 4, T, KIND, BUF>;
+            default: return nullptr;
+            }
+        }
         switch (lpr) {
         case 4: return mttkrp_kernel<NIN, 4, RPL, T, KIND, BUF>;
         case 8: return mttkrp_kernel<NIN, 8, RPL, T, KIND, BUF>;

@@ -79,6 +79,7 @@ constexpr int kMaxIn = kMaxOrder - 1;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 struct KParams {
     const int32_t* out_idx;
@@ -187,8 +188,10 @@ template <typename T, int RPL> struct Row;
 
 template <> struct Row<float, 4> {
     using Raw = float4;
-    static __device__ __forceinline__ Raw merge(const Raw& a, const u32x4& b)
+    // bitwise OR with the same lane's 16 bytes of an LDS row (one side is 0)
+    static __device__ __forceinline__ Raw merge_lds(const Raw& a, const char* lds)
     {
+        const u32x4 b = *reinterpret_cast<const u32x4*>(lds);
         return make_float4(__uint_as_float(__float_as_uint(a.x) | b.x), __uint_as_float(__float_as_uint(a.y) | b.y),
                            __uint_as_float(__float_as_uint(a.z) | b.z), __uint_as_float(__float_as_uint(a.w) | b.w));
     }
@@ -207,8 +210,9 @@ template <> struct Row<float, 4> {
 
 template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
     using Raw = uint4;
-    static __device__ __forceinline__ Raw merge(const Raw& a, const u32x4& b)
+    static __device__ __forceinline__ Raw merge_lds(const Raw& a, const char* lds)
     {
+        const u32x4 b = *reinterpret_cast<const u32x4*>(lds);
         return make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
     }
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
@@ -226,6 +230,29 @@ template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
             v[2 * i] = __uint_as_float(w[i] << 16);
             v[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
         }
+    }
+};
+
+template <> struct Row<uint16_t, 4> {  // 4 bfloat16 per lane (rows of up to 64 bytes)
+    using Raw = uint2;
+    static __device__ __forceinline__ Raw merge_lds(const Raw& a, const char* lds)
+    {
+        const u32x2 b = *reinterpret_cast<const u32x2*>(lds);
+        return make_uint2(a.x | b.x, a.y | b.y);
+    }
+    static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AMPED_GATHER_AUX);
+        return make_uint2(v.x, v.y);
+    }
+    static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint2*>(a); }
+    static __device__ __forceinline__ Raw zero() { return make_uint2(0u, 0u); }
+    static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
+    {
+        v[0] = __uint_as_float(r.x << 16);
+        v[1] = __uint_as_float(r.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(r.y << 16);
+        v[3] = __uint_as_float(r.y & 0xFFFF0000u);
     }
 };
 
@@ -420,8 +447,9 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
 #pragma unroll
                 for (int w = 0; w < NIN; ++w) {
                     for (int i = threadIdx.x; i < K; i += kMttkrpBlock) tag[w * K + i] = p.hot[w][i];
-                    for (int i = threadIdx.x; i < K * LPR; i += kMttkrpBlock) {
-                        const int slot = i / LPR, piece = i % LPR;
+                    constexpr int PR = RB / 16;   // 16-byte pieces per row
+                    for (int i = threadIdx.x; i < K * PR; i += kMttkrpBlock) {
+                        const int slot = i / PR, piece = i % PR;
                         const int row = p.hot[w][slot];
                         u32x4 v = {0u, 0u, 0u, 0u};
                         if (row >= 0)
@@ -442,8 +470,9 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         if constexpr (BUF) r = RowT::load_buf(rsrc[w], (uint32_t)max(ix, -1) * (uint32_t)rb + cb);
         else r = RowT::load_ptr(ix < 0 ? zrow : lbase[w] + (uint64_t)(uint32_t)ix * rb);
         if constexpr (VEC && KIND == 0) {
-            const uint32_t la = ix <= -2 ? hrow + (uint32_t)(w * K + (-2 - ix)) * RB + (uint32_t)s * 16u : 0u;
-            r = RowT::merge(r, *reinterpret_cast<const u32x4*>(s_dyn + la));
+            constexpr uint32_t LB = RPL * sizeof(T);   // bytes per lane
+            const uint32_t la = ix <= -2 ? hrow + (uint32_t)(w * K + (-2 - ix)) * RB + (uint32_t)s * LB : 0u;
+            r = RowT::merge_lds(r, s_dyn + la);
         }
         return r;
     };
