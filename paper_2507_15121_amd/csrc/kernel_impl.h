@@ -70,6 +70,10 @@ constexpr int kMaxIn = kMaxOrder - 1;
 #ifndef AMPED_MIN_WAVES
 #define AMPED_MIN_WAVES 0
 #endif
+// Spread each tile's metadata loads over its batch pairs (see the tile loop).
+#ifndef AMPED_META_SPREAD
+#define AMPED_META_SPREAD 1
+#endif
 #if AMPED_MIN_WAVES > 0
 #define AMPED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(AMPED_MIN_WAVES)))
 #else
@@ -558,6 +562,27 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
                     for (int f = 0; f < NF; ++f) vm[kq][f] = i32x4{0, 0, 0, 0};
             }
         };
+        // Items [L0, L1) of tile t's metadata (item l = 16-byte load kq = l / NF
+        // of field l % NF), issued whatever t is: past the last tile the offset
+        // is pushed out of the buffer (2^30 >= any chunk's metadata bytes), so
+        // the loads return zeros and cost no memory traffic.
+        auto load_meta_part = [&](int t, auto l0, auto l1) {
+            constexpr int L0 = decltype(l0)::value, L1 = decltype(l1)::value;
+            const uint32_t bias = t < ntiles ? 0u : (1u << 30);
+            static_for<L1 - L0>([&](auto li) {
+                constexpr int l = L0 + decltype(li)::value;
+                constexpr int kq = l / NF, f = l % NF;
+                const uint32_t off = (uint32_t)(goff + t * TS + kq * 4 * LPR + 4 * s) * 4u + bias;
+                if (vec_meta) {
+                    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(mr[f], (int)off, 0, kMetaNT);
+                    vm[kq][f] = i32x4{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        vm[kq][f][e] = (int)__builtin_amdgcn_raw_buffer_load_b32(mr[f], (int)(off + 4 * e), 0, kMetaNT);
+                }
+            });
+        };
         // tile t to ring slot t & 1, entries past the end of the run padded
         // here (a tile after its loads were issued, so they have landed)
         auto park_meta = [&](int t) {
@@ -674,7 +699,34 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
             }
         };
 
-        if (nbatch > 0) {
+        // With at most 8 batch pairs per tile, the tile is unrolled and the
+        // loads of tile t+2's metadata are spread over its batch pairs at
+        // fixed places, so every pass of the tile loop issues the same loads
+        // and the compiler's load-counter waits are exact; otherwise tile
+        // t+2 is loaded at once at the start of tile t.
+        constexpr int IT = NB / 2;
+        constexpr bool SPREAD = AMPED_META_SPREAD != 0 && IT <= 8;
+        if (SPREAD && nbatch > 0) {
+            constexpr int NL = Q4 * NF;
+            load_meta(0);
+            park_meta(0);
+            load_meta(1);
+            issue(0, rawA, ownA);
+#pragma unroll 1
+            for (int t = 0; t < ntiles; ++t) {
+                park_meta(t + 1);
+                static_for<IT>([&](auto kk) {
+                    constexpr int K = decltype(kk)::value;
+                    const int q = t * NB + 2 * K;
+                    issue(q + 1, rawB, ownB);
+                    load_meta_part(t + 2, std::integral_constant<int, K * NL / IT>{},
+                                   std::integral_constant<int, (K + 1) * NL / IT>{});
+                    consume(q, rawA, ownA);
+                    issue(q + 2, rawA, ownA);   // past the last batch: padding only
+                    consume(q + 1, rawB, ownB);
+                });
+            }
+        } else if (nbatch > 0) {
             load_meta(0);
             park_meta(0);
             load_meta(1);
