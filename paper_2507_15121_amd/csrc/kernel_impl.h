@@ -67,6 +67,9 @@ constexpr int kMaxIn = kMaxOrder - 1;
 #ifndef AMPED_UMAX_OWN
 #define AMPED_UMAX_OWN 2
 #endif
+#ifndef AMPED_UMAX_NIN
+#define AMPED_UMAX_NIN 2   // most input modes that still get AMPED_UMAX
+#endif
 #ifndef AMPED_MIN_WAVES
 #define AMPED_MIN_WAVES 0
 #endif
@@ -385,7 +388,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     constexpr int RT = LPR * RPL;
     // nonzeros per group per batch: the forms that also read the output
     // mode's row, and high orders, keep fewer rows in flight per batch
-    constexpr int U = (KIND == 0 && NIN <= 2) ? AMPED_UMAX : AMPED_UMAX_OWN;
+    constexpr int U = (KIND == 0 && NIN <= AMPED_UMAX_NIN) ? AMPED_UMAX : AMPED_UMAX_OWN;
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
     constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
     constexpr int NB = TS / U;                                   // batches per tile (even)
