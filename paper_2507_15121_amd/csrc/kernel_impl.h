@@ -10,8 +10,8 @@
 //    Sec. 4.2: each wave takes the next chunk from a device atomic counter
 //    until none is left, so skewed slices spread over all CUs.
 //  * Inside a chunk the wave is G groups of LPR lanes.  Each lane holds RPL
-//    consecutive columns of a factor row (16 bytes), so a group loads a whole
-//    row with one coalesced access.  Group g walks its own contiguous run of
+//    consecutive columns of a factor row (16 bytes; 8 for bf16 rows of up to
+//    64 bytes), so a group loads a whole row with one coalesced access.  Group g walks its own contiguous run of
 //    the chunk's nonzeros in order and keeps the running sum of the current
 //    output row in registers (the elementwise computation, EC of Sec. 3,
 //    reduced over consecutive equal output indices instead of one atomic per
@@ -22,12 +22,12 @@
 //    boundary are added to memory with fp32 atomics (Sec. 3.2 uses atomics
 //    between SMs), after the init kernel has zeroed them.
 //  * Untouched output rows are zeroed once, by the init kernel.
+//  * MTTKRP keeps the most-used rows of each input factor in LDS (hot-row
+//    cache); their gathers issue no memory request.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <mutex>
 #include <type_traits>
-#include <unordered_map>
 #include <utility>
 
 #include "internal.h"
@@ -47,8 +47,8 @@ constexpr int kBlock = 256;  // init and permute kernels
 #define AMPED_BLOCK_OWN 256
 #endif
 __host__ __device__ constexpr int mttkrp_block(int kind) { return kind == 0 ? AMPED_BLOCK : AMPED_BLOCK_OWN; }
-// Output rows are written with non-temporal stores (compile-time knob), and
-// factor-row gathers with this cache policy.
+// Compile-time knobs, off by default (both measured slower): non-temporal
+// output-row stores, and the cache-policy bits of factor-row gathers.
 #ifndef AMPED_OUT_NT
 #define AMPED_OUT_NT 0
 #endif
@@ -138,46 +138,6 @@ __device__ __forceinline__ void static_for(F&& f)
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// Value of lane (group base + J) for every lane of an LPR-lane group.
-template <int LPR, int J>
-__device__ __forceinline__ int group_bcast(int x)
-{
-    if constexpr (LPR == 1) {
-        return x;
-    } else if constexpr (LPR == 64) {
-        return __builtin_amdgcn_readlane(x, J);
-    } else {
-        // ds_swizzle bit mode inside 32-lane halves: lane' = (lane & and) | or
-        constexpr int and_mask = 0x1F & ~(LPR - 1);
-        return __builtin_amdgcn_ds_swizzle(x, and_mask | (J << 5));
-    }
-}
-template <int LPR, int J>
-__device__ __forceinline__ float group_bcast_f(float x)
-{
-    return __int_as_float(group_bcast<LPR, J>(__float_as_int(x)));
-}
-
-// Broadcast of lane (group base + jb*U + JU).  One batch per tile: compile-time
-// ds_swizzle.  Several batches: the batch index is a run-time (wave-uniform)
-// loop counter, so ds_bpermute, or v_readlane when the group is the wave.
-template <int LPR, int U, int NB, int JU>
-__device__ __forceinline__ int tile_bcast(int x, int jb, int lane)
-{
-    if constexpr (NB == 1) {
-        return group_bcast<LPR, JU>(x);
-    } else if constexpr (LPR == 64) {
-        return __builtin_amdgcn_readlane(x, jb * U + JU);
-    } else {
-        return __builtin_amdgcn_ds_bpermute(((lane & ~(LPR - 1)) + jb * U + JU) << 2, x);
-    }
-}
-template <int LPR, int U, int NB, int JU>
-__device__ __forceinline__ float tile_bcast_f(float x, int jb, int lane)
-{
-    return __int_as_float(tile_bcast<LPR, U, NB, JU>(__float_as_int(x), jb, lane));
-}
-
 template <int LPR>
 __device__ __forceinline__ float group_sum(float x)
 {
@@ -208,7 +168,6 @@ template <> struct Row<float, 4> {
         return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
     }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const float4*>(a); }
-    static __device__ __forceinline__ Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
     {
         v[0] = r.x; v[1] = r.y; v[2] = r.z; v[3] = r.w;
@@ -228,7 +187,6 @@ template <> struct Row<uint16_t, 8> {  // bfloat16 bit patterns, widened exactly
         return make_uint4(v.x, v.y, v.z, v.w);
     }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint4*>(a); }
-    static __device__ __forceinline__ Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[8])
     {
         const uint32_t w[4] = {r.x, r.y, r.z, r.w};
@@ -253,7 +211,6 @@ template <> struct Row<uint16_t, 4> {  // 4 bfloat16 per lane (rows of up to 64 
         return make_uint2(v.x, v.y);
     }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint2*>(a); }
-    static __device__ __forceinline__ Raw zero() { return make_uint2(0u, 0u); }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[4])
     {
         v[0] = __uint_as_float(r.x << 16);
@@ -267,7 +224,6 @@ template <> struct Row<float, 1> {
     using Raw = float;
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0.f; }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const float*>(a); }
-    static __device__ __forceinline__ Raw zero() { return 0.f; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = r; }
 };
 
@@ -275,7 +231,6 @@ template <> struct Row<uint16_t, 1> {
     using Raw = uint32_t;
     static __device__ __forceinline__ Raw load_buf(__amdgpu_buffer_rsrc_t, uint32_t) { return 0u; }
     static __device__ __forceinline__ Raw load_ptr(const char* a) { return *reinterpret_cast<const uint16_t*>(a); }
-    static __device__ __forceinline__ Raw zero() { return 0u; }
     static __device__ __forceinline__ void unpack(const Raw& r, float (&v)[1]) { v[0] = __uint_as_float(r << 16); }
 };
 
