@@ -19,8 +19,10 @@ from paper_2507_15121_amd.autograd import SparseCPLoss  # noqa: E402
 
 # ------------------------------------------------------------------ bfloat16
 
-@pytest.mark.parametrize("rank", [32, 64, 128, 5, 40])
+@pytest.mark.parametrize("rank", [32, 64, 128, 5, 40, 16, 8])
 def test_bf16_factors(rank):
+    """16 and 32: 8-byte lanes (rows of up to 64 bytes); 64 and 128: 16-byte
+    lanes; 5, 8 and 40: the column-tile path."""
     dims = (20000, 5000, 3000)
     st = synth.tensor(dims, 80000, "zipf", 1.1, 0.05, seed=21)
     factors = synth.factors(dims, rank, seed=21)

@@ -117,3 +117,45 @@ def test_factor_above_4GiB_uses_64bit_gathers():
         assert e <= 1e-5
         assert not torch.isnan(out).any().item()
     T.close()
+
+
+def test_bf16_factor_above_4GiB_narrow_lanes():
+    """bf16 factors at rank 32 (64-byte rows, 8-byte lanes): a 72M-row factor is
+    4.6 GB, past 32-bit buffer offsets, so modes 1 and 2 gather it with 64-bit
+    addresses.  The oracle sees the same bf16 values (exactly widened) on the
+    rows the sampled outputs use."""
+    dims = (72_000_000, 1000, 500)
+    R = 32
+    st = synth.tensor(dims, 2_000_000, "zipf", 1.1, 0.0, seed=13)
+    T = api.Tensor(st.idx, st.val, dims)
+    rng = np.random.default_rng(13)
+    dbf = []
+    for d in dims:
+        f = torch.empty((d, R), device="cuda").uniform_(-1, 1)
+        dbf.append(f.to(torch.bfloat16))
+        del f
+    for d in (1, 2):
+        out = torch.full((dims[d], R), float("nan"), device="cuda")
+        api.mttkrp_bf16(T, d, [None if w == d else f for w, f in enumerate(dbf)], out=out)
+        torch.cuda.synchronize()
+        rows, _, _ = _sample_rows(st, d, rng, 200)
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        m = np.isin(st.idx[d], rows)
+        sub = st.idx[:, m].astype(np.int64)
+        fs, cdims = [], []
+        for w in range(3):
+            if w == d:
+                sub[w] = np.searchsorted(rows, sub[w])
+                fs.append(np.zeros((rows.size, R)))
+                cdims.append(rows.size)
+            else:
+                used = np.unique(sub[w])
+                fs.append(dbf[w][torch.from_numpy(used).cuda()].float().double().cpu().numpy())
+                sub[w] = np.searchsorted(used, sub[w])
+                cdims.append(used.size)
+        ref = oracle.mttkrp(sub.astype(np.int32), st.val[m], cdims, fs, d)
+        e = oracle.rel_fro(got, ref)
+        log("4.6 GB bf16 factor, mode %d: sampled rel %.2e" % (d, e))
+        assert e <= 1e-5
+        assert not torch.isnan(out).any().item()
+    T.close()
