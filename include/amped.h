@@ -214,12 +214,17 @@ amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void 
  *            16-byte aligned; read, and factors[d] overwritten in mode order
  *   lambda   DEVICE, rank doubles (16-byte aligned), overwritten
  *   fit      DEVICE, one double, overwritten
+ *   flags    AMPED_ALS_REUSE_GRAMS: the factors are exactly those the
+ *            previous sweep on this tensor, at this rank, left; the Gram
+ *            matrices it kept are used instead of being recomputed (INVALID
+ *            if there is no such sweep).  0 otherwise.
  * 1 <= rank <= 128.  The tensor keeps a workspace for the rank of its last
  * sweep (max_d dims[d] x rank floats plus small R x R arrays); sweeps on one
  * tensor must not overlap.
  */
+#define AMPED_ALS_REUSE_GRAMS 1u
 amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float *const *factors, double *lambda,
-                                double *fit, void *stream);
+                                double *fit, unsigned flags, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *amped_last_error(void);

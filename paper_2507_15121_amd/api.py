@@ -58,7 +58,7 @@ def lib():
         L.amped_cp_loss.argtypes = [vp, i32, pvp, vp, vp]
         L.amped_cp_grad.argtypes = [vp, i32, i32, pvp, ctypes.c_float, vp, vp]
         L.amped_gram.argtypes = [vp, i64, i32, vp, vp]
-        L.amped_cp_als_sweep.argtypes = [vp, i32, pvp, vp, vp, vp]
+        L.amped_cp_als_sweep.argtypes = [vp, i32, pvp, vp, vp, ctypes.c_uint, vp]
         for name in EXPORTED:
             if name not in ("amped_last_error", "amped_version"):
                 getattr(L, name).restype = ctypes.c_int
@@ -272,9 +272,14 @@ def gram(A, out=None, stream=None):
     return out
 
 
-def cp_als_sweep(t: Tensor, factors, lam=None, fit=None, stream=None):
+ALS_REUSE_GRAMS = 1
+
+
+def cp_als_sweep(t: Tensor, factors, lam=None, fit=None, reuse_grams=False, stream=None):
     """One CP-ALS sweep over all modes; factors (float32 device tensors) are
-    updated in place.  Returns (lambda, fit) as float64 device tensors."""
+    updated in place.  Returns (lambda, fit) as float64 device tensors.
+    reuse_grams: the factors are exactly what the previous sweep on this
+    tensor left, so its Gram matrices are reused."""
     torch = _torch()
     ptrs, rank = _ptr_array(t, factors, torch.float32, None)
     dev = factors[0].device
@@ -285,5 +290,6 @@ def cp_als_sweep(t: Tensor, factors, lam=None, fit=None, stream=None):
     if lam.dtype != torch.float64 or lam.numel() != rank or fit.dtype != torch.float64 or fit.numel() != 1:
         raise ValueError("lambda must hold rank float64 values and fit one float64")
     _check(lib().amped_cp_als_sweep(t.handle, rank, ptrs, ctypes.c_void_p(lam.data_ptr()),
-                                    ctypes.c_void_p(fit.data_ptr()), _stream_ptr(stream)))
+                                    ctypes.c_void_p(fit.data_ptr()), ALS_REUSE_GRAMS if reuse_grams else 0,
+                                    _stream_ptr(stream)))
     return lam, fit

@@ -47,6 +47,27 @@ __device__ __forceinline__ float pick(const float (&x)[T], int t)
     return r;
 }
 
+// Upper-triangle tile pair p of T x T tiles (G is symmetric): row-major over
+// tm <= tn.
+__host__ __device__ constexpr int tri_tm(int T, int p)
+{
+    int tm = 0;
+    while (p >= T - tm) {
+        p -= T - tm;
+        ++tm;
+    }
+    return tm;
+}
+__host__ __device__ constexpr int tri_tn(int T, int p)
+{
+    int tm = 0;
+    while (p >= T - tm) {
+        p -= T - tm;
+        ++tm;
+    }
+    return tm + p;
+}
+
 // T = number of 32-column tiles (R <= 32 T).  Grid (slabs, tile groups);
 // four waves per block each take a quarter of the slab's rows and keep up to
 // kGramMaxPairs 32x32 tiles in MFMA accumulators, with kGramBatch row pairs of
@@ -57,7 +78,7 @@ template <int T>
 __global__ void __launch_bounds__(256) gram_partial(const float* A, int64_t rows, int R, int64_t slab_rows,
                                                     float* partial)
 {
-    constexpr int NP = T * T;
+    constexpr int NP = T * (T + 1) / 2;                               // upper-triangle tiles
     constexpr int NPB = NP < kGramMaxPairs ? NP : kGramMaxPairs;   // tiles per block
     constexpr int B = T <= 2 ? kGramBatch : kGramBatch / 2;          // row pairs per load batch
     __shared__ float s_t[4][NPB][32 * 32];
@@ -97,8 +118,8 @@ __global__ void __launch_bounds__(256) gram_partial(const float* A, int64_t rows
             for (int j = 0; j < NPB; ++j) {
                 if (j < np) {
                     const int p = p0 + j;
-                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick<T>(x[u], p / T), pick<T>(x[u], p % T), acc[j],
-                                                                  0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick<T>(x[u], tri_tm(T, p)),
+                                                                  pick<T>(x[u], tri_tn(T, p)), acc[j], 0, 0, 0);
                 }
             }
     };
@@ -123,8 +144,11 @@ __global__ void __launch_bounds__(256) gram_partial(const float* A, int64_t rows
         const int j = e >> 10, m = (e >> 5) & 31, n = e & 31;
         const float sum = ((s_t[0][j][e & 1023] + s_t[1][j][e & 1023]) + s_t[2][j][e & 1023]) + s_t[3][j][e & 1023];
         const int p = p0 + j;
-        const int r = (p / T) * 32 + m, c = (p % T) * 32 + n;
-        if (r < R && c < R) out[r * R + c] = sum;
+        const int r = tri_tm(T, p) * 32 + m, c = tri_tn(T, p) * 32 + n;
+        if (r < R && c < R) {
+            out[r * R + c] = sum;
+            out[c * R + r] = sum;   // the mirrored tile (the same entry on the diagonal tiles)
+        }
     }
 }
 
@@ -374,7 +398,7 @@ hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, doub
     int64_t slab_rows = (rows + nslab - 1) / nslab;
     slab_rows += slab_rows & 1;
     const int T = (R + 31) / 32;
-    const int groups = (T * T + kGramMaxPairs - 1) / kGramMaxPairs;
+    const int groups = (T * (T + 1) / 2 + kGramMaxPairs - 1) / kGramMaxPairs;
     dim3 grid((unsigned)nslab, (unsigned)groups);
     switch (T) {
     case 1: hipLaunchKernelGGL(gram_partial<1>, grid, dim3(256), 0, st, A, rows, R, slab_rows, partial); break;

@@ -85,6 +85,7 @@ struct amped_tensor_s {
         float* W = nullptr;        // R x R
         double* xnorm2 = nullptr;  // ||X||^2 (computed once)
         bool have_xnorm2 = false;
+        bool have_grams = false;   // G matches the factors the last sweep wrote
     } als;
 
     hipError_t alloc(void** p, size_t bytes)
@@ -560,13 +561,17 @@ amped_status amped_gram(const float* A, int64_t rows, int rank, double* G, void*
 }
 
 amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factors, double* lambda, double* fit,
-                                void* stream)
+                                unsigned flags, void* stream)
 {
     g_err.clear();
     amped_status st = check_call(t, 0, rank, reinterpret_cast<const void* const*>(factors), lambda, true, "lambda");
     if (st != AMPED_OK) return st;
     if (rank > 128) return fail(AMPED_ERR_INVALID, "rank %d above 128 (CP-ALS)", rank);
     if (!fit) return fail(AMPED_ERR_INVALID, "fit is NULL");
+    if (flags & ~AMPED_ALS_REUSE_GRAMS) return fail(AMPED_ERR_INVALID, "unknown flags 0x%x", flags);
+    const bool reuse = (flags & AMPED_ALS_REUSE_GRAMS) != 0;
+    if (reuse && (t->als.rank != rank || !t->als.have_grams))
+        return fail(AMPED_ERR_INVALID, "no previous sweep at rank %d to reuse Gram matrices from", rank);
     DeviceGuard guard(t->device);
     if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -609,9 +614,12 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
             return hip_fail(e, "tensor norm");
         w.have_xnorm2 = true;
     }
-    for (int m = 0; m < N; ++m)
-        if ((e = amped::launch_gram(factors[m], t->dims[m], rank, w.partial, w.G + m * RR, s)) != hipSuccess)
-            return hip_fail(e, "gram");
+    w.have_grams = false;   // stays false if the sweep stops part-way
+    if (!reuse) {
+        for (int m = 0; m < N; ++m)
+            if ((e = amped::launch_gram(factors[m], t->dims[m], rank, w.partial, w.G + m * RR, s)) != hipSuccess)
+                return hip_fail(e, "gram");
+    }
     for (int d = 0; d < N; ++d) {
         st = run_mttkrp(t, d, rank, reinterpret_cast<const void* const*>(factors), w.M, stream,
                         amped::FactorType::F32, amped::Kind::Mttkrp, 1.0f);
@@ -624,6 +632,7 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
         if ((e = amped::launch_als_solve(w.M, w.W, factors[d], t->dims[d], rank, s)) != hipSuccess)
             return hip_fail(e, "als solve");
     }
+    w.have_grams = true;   // G now holds the Gram matrices of the factors just written
     return AMPED_OK;
 }
 

@@ -135,7 +135,7 @@ def test_calls_with_null_handle_are_rejected():
     assert L.amped_mttkrp_bf16(None, 0, 32, ptrs, None, None) == api.ERR_INVALID
     assert L.amped_cp_loss(None, 32, ptrs, None, None) == api.ERR_INVALID
     assert L.amped_cp_grad(None, 0, 32, ptrs, ctypes.c_float(1.0), None, None) == api.ERR_INVALID
-    assert L.amped_cp_als_sweep(None, 32, ptrs, None, None, None) == api.ERR_INVALID
+    assert L.amped_cp_als_sweep(None, 32, ptrs, None, None, 0, None) == api.ERR_INVALID
     assert L.amped_gram(None, 10, 32, None, None) == api.ERR_INVALID
     fake = ctypes.c_void_p(16)   # never dereferenced: the size checks come first
     assert L.amped_gram(fake, 0, 32, fake, None) == api.ERR_INVALID

@@ -76,9 +76,12 @@ def test_one_sweep_vs_oracle(rank):
     assert abs(fit - fo) <= 1e-5
 
 
-def test_sweeps_track_oracle_and_fit_rises():
+@pytest.mark.parametrize("reuse", [False, True])
+def test_sweeps_track_oracle_and_fit_rises(reuse):
     """A sparse sample of an exact rank-4 model plus 1% noise: 8 sweeps from a
-    random start, each compared with the oracle's sweep from the same start."""
+    random start, each compared with the oracle's sweep from the same start.
+    reuse: every sweep after the first takes the Gram matrices the one before
+    left (computed from M and the update, not from the stored factors)."""
     dims = (800, 600, 500)
     rng = np.random.default_rng(50)
     U = [rng.uniform(0.1, 1.0, (d, 4)) for d in dims]
@@ -92,7 +95,7 @@ def test_sweeps_track_oracle_and_fit_rises():
     fits = []
     for s in range(8):
         start = [f.cpu().numpy().astype(np.float64) for f in dF]
-        lam, fit = api.cp_als_sweep(t, dF)
+        lam, fit = api.cp_als_sweep(t, dF, reuse_grams=reuse and s > 0)
         Fo, lo, fo = als.cp_als_sweep(idx, val, dims, start)
         f = float(fit.item())
         log("sweep %d fit %.6f oracle %.6f" % (s, f, fo))
@@ -146,3 +149,20 @@ def test_order_four():
     errs = [oracle.rel_fro(F[d], Fo[d]) for d in range(4)]
     log("order 4: errs %s fit %.6f vs %.6f" % (["%.1e" % e for e in errs], fit, fo))
     assert max(errs) <= 1e-4 and abs(fit - fo) <= 1e-5
+
+
+def test_reuse_needs_a_previous_sweep_at_that_rank():
+    dims = (300, 200, 100)
+    st = synth.tensor(dims, 5000, "zipf", 1.1, 0.0, seed=90)
+    t = api.Tensor(st.idx, st.val, dims)
+    rng = np.random.default_rng(9)
+    dF = [_dev(rng.uniform(-1, 1, (d, 8))) for d in dims]
+    with pytest.raises(api.AmpedError):
+        api.cp_als_sweep(t, dF, reuse_grams=True)          # no sweep yet
+    api.cp_als_sweep(t, dF)
+    api.cp_als_sweep(t, dF, reuse_grams=True)
+    dG = [_dev(rng.uniform(-1, 1, (d, 16))) for d in dims]
+    with pytest.raises(api.AmpedError):
+        api.cp_als_sweep(t, dG, reuse_grams=True)          # another rank
+    torch.cuda.synchronize()
+    t.close()
