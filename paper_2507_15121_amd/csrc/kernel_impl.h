@@ -470,8 +470,10 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         int first_open = 1;  // the open row is the run's first
         int lsh = 0;         // the run's first row continues from the previous position
         float acc[RPL];
+        float cur_own[RPL];  // own row of the entry consumed last (forms that read it)
+        int own_key = -1;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) acc[i] = 0.f;
+        for (int i = 0; i < RPL; ++i) acc[i] = cur_own[i] = 0.f;
         if constexpr (OUT) {
             if (gon) {
                 const int first = p.out_idx[gs];
@@ -588,12 +590,22 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
 #pragma unroll
             for (int w = 0; w < NIN; ++w) lds_vec<U>(mrow + (1 + w) * FS, ix[w]);
             int kk[U];
-            if constexpr (OWN) lds_vec<U>(mrow, kk);
+            int kprev = 0;   // key of the entry before the batch (same tile)
+            if constexpr (OWN) {
+                lds_vec<U>(mrow, kk);
+                kprev = mrow[j0 > 0 ? -1 : 0];
+            }
 #pragma unroll
             for (int ju = 0; ju < U; ++ju) {
 #pragma unroll
                 for (int w = 0; w < NIN; ++w) raw[ju][w] = gather(w, ix[w][ju]);
-                if constexpr (OWN) own[ju] = gather_own(ix[0][ju] == -1 ? -1 : kk[ju]);  // -1: padding
+                if constexpr (OWN) {
+                    // the own row is read where the key changes (and at a
+                    // tile's first entry); elsewhere consume reuses the row
+                    // it holds, and the load, at -1, returns zeros
+                    const bool same = j0 + ju > 0 && kk[ju] == (ju == 0 ? kprev : kk[ju > 0 ? ju - 1 : 0]);
+                    own[ju] = gather_own((ix[0][ju] == -1 || same) ? -1 : kk[ju]);  // -1: padding
+                }
             }
         };
 
@@ -617,7 +629,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
             const int j0 = (q % NB) * U;
             const int* mrow = &s_meta[wv][t & 1][0][g * TS + j0];
             int key[U], vbits[U];
-            if constexpr (OUT) lds_vec<U>(mrow, key);
+            if constexpr (OUT || OWN) lds_vec<U>(mrow, key);
             lds_vec<U>(mrow + (NF - 1) * FS, vbits);
 #pragma unroll
             for (int ju = 0; ju < U; ++ju) {
@@ -633,11 +645,17 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
                 }
                 float coef = val;
                 if constexpr (OWN) {
+                    // same rule as in issue: a fresh row where the key changes
+                    // or the tile starts, else the row of the previous entry
+                    const bool fresh = j0 + ju == 0 || key[ju] != own_key;
                     float ow[RPL];
                     OwnRow::unpack(own[ju], ow);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) cur_own[i] = fresh ? ow[i] : cur_own[i];
+                    own_key = key[ju];
                     float part = 0.f;
 #pragma unroll
-                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], ow[i], part);
+                    for (int i = 0; i < RPL; ++i) part = fmaf(prod[i], cur_own[i], part);
                     if constexpr (!VEC) part = lane_on ? part : 0.f;
                     coef = val - group_sum<LPR>(part);
                 }
