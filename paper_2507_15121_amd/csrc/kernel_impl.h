@@ -47,6 +47,11 @@ constexpr int kBlock = 256;  // init and permute kernels
 #define AMPED_BLOCK_OWN 256
 #endif
 __host__ __device__ constexpr int mttkrp_block(int kind) { return kind == 0 ? AMPED_BLOCK : AMPED_BLOCK_OWN; }
+// The residual and loss forms keep hot rows in LDS too (else MTTKRP only).
+#ifndef AMPED_HOT_OWN
+#define AMPED_HOT_OWN 0
+#endif
+__host__ __device__ constexpr bool hot_cache_kind(int kind) { return kind == 0 || AMPED_HOT_OWN != 0; }
 // Compile-time knobs, off by default (both measured slower): non-temporal
 // output-row stores, and the cache-policy bits of factor-row gathers.
 #ifndef AMPED_OUT_NT
@@ -58,11 +63,14 @@ __host__ __device__ constexpr int mttkrp_block(int kind) { return kind == 0 ? AM
 constexpr int kMaxIn = kMaxOrder - 1;
 
 // Tuning knobs (compile-time): nonzeros per group whose gathers are issued
-// together (MTTKRP with up to 2 input modes; the residual/loss forms and
-// higher orders use the second value), and the waves per SIMD the register
-// allocation must allow (0 = compiler's choice).
+// together (MTTKRP, then the residual gradient, with up to 2 input modes; the
+// loss and higher orders use the third value), and the waves per SIMD the
+// register allocation must allow (0 = compiler's choice).
 #ifndef AMPED_UMAX
 #define AMPED_UMAX 4
+#endif
+#ifndef AMPED_UMAX_GRAD
+#define AMPED_UMAX_GRAD 4
 #endif
 #ifndef AMPED_UMAX_OWN
 #define AMPED_UMAX_OWN 2
@@ -343,7 +351,8 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     constexpr int RT = LPR * RPL;
     // nonzeros per group per batch: the forms that also read the output
     // mode's row, and high orders, keep fewer rows in flight per batch
-    constexpr int U = (KIND == 0 && NIN <= AMPED_UMAX_NIN) ? AMPED_UMAX : AMPED_UMAX_OWN;
+    constexpr int U = (KIND != 2 && NIN <= AMPED_UMAX_NIN) ? (KIND == 0 ? AMPED_UMAX : AMPED_UMAX_GRAD)
+                                                          : AMPED_UMAX_OWN;
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
     constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
     constexpr int NB = TS / U;                                   // batches per tile (even)
@@ -398,12 +407,12 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     // entries that name a cached row are rewritten to -2 - slot when parked.
     extern __shared__ __align__(16) char s_dyn[];
     constexpr int RB = RT * (int)sizeof(T);  // row bytes on the vector path
-    const int K = (VEC && KIND == 0) ? p.hot_k : 0;
+    const int K = (VEC && hot_cache_kind(KIND)) ? p.hot_k : 0;
     const int* const htag = reinterpret_cast<const int*>(s_dyn + hot_tag_offset());
     const uint32_t hrow = (uint32_t)hot_row_offset(NIN, K);  // byte offset of the cached rows
     {
         if (threadIdx.x < 4) reinterpret_cast<int*>(s_dyn)[threadIdx.x] = 0;
-        if constexpr (VEC && KIND == 0) {
+        if constexpr (VEC && hot_cache_kind(KIND)) {
             if (K > 0) {
                 int* tag = reinterpret_cast<int*>(s_dyn + hot_tag_offset());
 #pragma unroll
@@ -431,7 +440,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         typename RowT::Raw r;
         if constexpr (BUF) r = RowT::load_buf(rsrc[w], (uint32_t)max(ix, -1) * (uint32_t)rb + cb);
         else r = RowT::load_ptr(ix < 0 ? zrow : lbase[w] + (uint64_t)(uint32_t)ix * rb);
-        if constexpr (VEC && KIND == 0) {
+        if constexpr (VEC && hot_cache_kind(KIND)) {
             constexpr uint32_t LB = RPL * sizeof(T);   // bytes per lane
             const uint32_t la = ix <= -2 ? hrow + (uint32_t)(w * K + (-2 - ix)) * RB + (uint32_t)s * LB : 0u;
             r = RowT::merge_lds(r, s_dyn + la);
@@ -557,7 +566,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
                     for (int w = 0; w < NIN; ++w) vm[kq][1 + w][e] = pad ? -1 : vm[kq][1 + w][e];
                     vm[kq][NF - 1][e] = pad ? 0 : vm[kq][NF - 1][e];
                 }
-                if constexpr (VEC && KIND == 0) {
+                if constexpr (VEC && hot_cache_kind(KIND)) {
                     if (K > 0) {
                         // rows held in the LDS cache become -2 - slot (tags
                         // are rows or -2, so padding -1 never matches)

@@ -242,7 +242,7 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
     k.ld = a.rank;
     k.scale = a.scale;
     const int block = mttkrp_block(a.kind == Kind::Mttkrp ? 0 : 1);
-    const Shape sh = launch_shape(fn, block, a.nin, a.rank * eb, !scalar && a.kind == Kind::Mttkrp);
+    const Shape sh = launch_shape(fn, block, a.nin, a.rank * eb, !scalar && hot_cache_kind(a.kind == Kind::Mttkrp ? 0 : 1));
     if (sh.grid <= 0) return hipErrorInvalidDevice;
     set_hot(k, sh.hot_k, a.in_hot, a.nin);
     const int tile = scalar ? 64 : a.rank;
@@ -287,7 +287,7 @@ hipError_t launch_cp_loss(const LossArgs& a)
     if (e != hipSuccess) return e;
     if (m.n_chunks == 0) return hipSuccess;
     const int block = mttkrp_block(2);
-    const Shape sh = launch_shape(fn, block, a.order - 1, a.rank * 4, false);
+    const Shape sh = launch_shape(fn, block, a.order - 1, a.rank * 4, !scalar && hot_cache_kind(2));
     if (sh.grid <= 0) return hipErrorInvalidDevice;
     set_hot(k, sh.hot_k, a.in_hot, a.order - 1);
     void* args[] = {&k};
