@@ -64,7 +64,16 @@ typedef struct {
                                  need more device bytes than this.                     */
     int32_t keep_perm;        /* 1 = keep each mode's permutation on the device so
                                  amped_tensor_layout can return it.                    */
-    int32_t reserved;         /* must be 0 */
+    int32_t host_layout;      /* 1 = keep the per-mode layouts in pinned host memory
+                                 (built by the host order builder) and stream them to
+                                 the device in shards on every call: for tensors whose
+                                 layouts do not fit in device memory (out-of-core
+                                 shard streaming, Sec. 4.8).  The device then holds
+                                 two shard buffers and the per-mode row lists only.
+                                 Results equal those of a device-resident tensor up
+                                 to fp32 summation order.  0 = device-resident.      */
+    int64_t shard_nnz;        /* host_layout: nonzeros per streamed shard, rounded up
+                                 to whole chunks; 0 = 2^25.  Ignored otherwise.       */
 } amped_options;
 
 /*

@@ -33,7 +33,7 @@ class AmpedError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("chunk_nnz", ctypes.c_int64), ("device_byte_cap", ctypes.c_int64),
-                ("keep_perm", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("keep_perm", ctypes.c_int32), ("host_layout", ctypes.c_int32), ("shard_nnz", ctypes.c_int64)]
 
 
 _lib = None
@@ -106,14 +106,18 @@ def layout_host(indices, dims, mode, chunk_nnz):
 
 
 class Tensor:
-    """A sparse tensor whose per-mode layouts live on the current HIP device."""
+    """A sparse tensor whose per-mode layouts live on the current HIP device,
+    or (host_layout=True) in pinned host memory, streamed to the device in
+    shards of shard_nnz nonzeros on every call."""
 
-    def __init__(self, indices, values, dims, chunk_nnz=0, keep_perm=False, device_byte_cap=0):
+    def __init__(self, indices, values, dims, chunk_nnz=0, keep_perm=False, device_byte_cap=0,
+                 host_layout=False, shard_nnz=0):
         idx, val, d = _host_coo(indices, values, dims)
         order, nnz = idx.shape
         if val.shape != (nnz,):
             raise ValueError("values must have one entry per nonzero")
-        opts = _Options(int(chunk_nnz), int(device_byte_cap), 1 if keep_perm else 0, 0)
+        opts = _Options(int(chunk_nnz), int(device_byte_cap), 1 if keep_perm else 0, 1 if host_layout else 0,
+                        int(shard_nnz))
         h = ctypes.c_void_p()
         self._h = None
         _check(lib().amped_tensor_create(order, d.ctypes.data, nnz, idx.ctypes.data if nnz else None,

@@ -430,9 +430,9 @@ hipError_t launch_als_solve(const float* M, const float* W, float* A, int64_t ro
     return hipGetLastError();
 }
 
-hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, hipStream_t st)
+hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, bool accumulate, hipStream_t st)
 {
-    hipError_t e = hipMemsetAsync(result, 0, sizeof(double), st);
+    hipError_t e = accumulate ? hipSuccess : hipMemsetAsync(result, 0, sizeof(double), st);
     if (e != hipSuccess || m.nnz == 0) return e;
     InIdx ii{};
     for (int w = 0; w < nin; ++w) ii.p[w] = m.in_idx[w];

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -74,6 +75,20 @@ struct amped_tensor_s {
     int32_t* perm[kMaxOrder] = {};
     std::vector<uint8_t> flags[kMaxOrder];
     int64_t touched[kMaxOrder] = {};
+    // Host-resident layouts (options.host_layout): each mode's arrays in
+    // pinned host memory, streamed to two device staging buffers per call.
+    bool host_layout = false;
+    int64_t stage_len = 0;  // nonzeros per shard (whole chunks)
+    struct HostMode {
+        int32_t* out_idx = nullptr;
+        int32_t* in_idx[kMaxOrder - 1] = {};
+        float* val = nullptr;
+    } hmode[kMaxOrder];
+    std::vector<void*> pinned;
+    std::vector<int32_t> hperm[kMaxOrder];  // kept permutations (keep_perm)
+    void* stage[2] = {};                    // (order + 1) arrays of stage_len + 4 entries each
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t copied[2] = {}, consumed[2] = {}, call_start = nullptr;
     // CP-ALS workspace, allocated by the first sweep of a rank
     struct AlsWork {
         int rank = 0;
@@ -107,11 +122,31 @@ struct amped_tensor_s {
                 a = nullptr;
             }
     }
+    hipError_t host_alloc(void** p, size_t bytes)
+    {
+        *p = nullptr;
+        if (bytes == 0) return hipSuccess;
+        hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) pinned.push_back(*p);
+        return e;
+    }
     void free_all()
     {
         for (void* a : allocs)
             if (a) (void)hipFree(a);
         allocs.clear();
+        for (void* a : pinned) (void)hipHostFree(a);
+        pinned.clear();
+        for (hipEvent_t& ev : {std::ref(copied[0]), std::ref(copied[1]), std::ref(consumed[0]), std::ref(consumed[1]),
+                               std::ref(call_start)})
+            if (ev) {
+                (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
+        if (copy_stream) {
+            (void)hipStreamDestroy(copy_stream);
+            copy_stream = nullptr;
+        }
     }
 };
 
@@ -170,6 +205,171 @@ amped_status check_device(int* dev)
         }                                                \
     } while (0)
 
+// A mode's row lists (zero rows, hot-row tables, long gaps) to the device,
+// and its sizes.
+amped_status upload_tables(amped_tensor_s* t, ModeDev& m, int d, const HostModeLayout& lay, void* queues, void* aux)
+{
+    amped_status st = AMPED_OK;
+    void* p = nullptr;
+    if (!lay.zero_rows.empty()) {
+        HIP_OR_FAIL(t->alloc(&p, lay.zero_rows.size() * 4), "hipMalloc(zero rows)");
+        HIP_OR_FAIL(hipMemcpy(p, lay.zero_rows.data(), lay.zero_rows.size() * 4, hipMemcpyHostToDevice),
+                    "hipMemcpy(zero rows)");
+        m.zero_rows = static_cast<int32_t*>(p);
+    }
+    HIP_OR_FAIL(t->alloc(&p, lay.hot.size() * 4), "hipMalloc(hot rows)");
+    HIP_OR_FAIL(hipMemcpy(p, lay.hot.data(), lay.hot.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(hot rows)");
+    m.hot = static_cast<int32_t*>(p);
+    if (!lay.gaps.empty()) {
+        HIP_OR_FAIL(t->alloc(&p, lay.gaps.size() * 4), "hipMalloc(gaps)");
+        HIP_OR_FAIL(hipMemcpy(p, lay.gaps.data(), lay.gaps.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(gaps)");
+        m.gaps = static_cast<int32_t*>(p);
+    }
+    m.nnz = t->nnz;
+    m.chunk = t->chunk;
+    m.n_chunks = t->n_chunks;
+    m.rows = t->dims[d];
+    m.n_zero = (int64_t)lay.zero_rows.size();
+    m.zero_row = aux;
+    m.sink = static_cast<float*>(aux) + 4;
+    m.n_gaps = (int64_t)lay.gaps.size() / 2;
+    m.queue = static_cast<int*>(queues) + d;
+    t->flags[d] = lay.flags;
+    t->touched[d] = lay.touched;
+cleanup:
+    return st;
+}
+
+// Host-resident layouts: the host order builder sorts every mode, the layout
+// arrays are gathered into pinned host memory, and the device receives the
+// row lists, two shard staging buffers, a copy stream and its events.
+amped_status build_host_layout(amped_tensor_s* t, const int32_t* indices, const float* values)
+{
+    const int order = t->order;
+    const int64_t nnz = t->nnz;
+    amped_status st = AMPED_OK;
+    void* queues = nullptr;
+    void* aux = nullptr;
+    void* p = nullptr;
+    HIP_OR_FAIL(t->alloc(&queues, (size_t)(order + 1) * sizeof(int)), "hipMalloc(queues)");
+    HIP_OR_FAIL(hipMemset(queues, 0, (size_t)(order + 1) * sizeof(int)), "hipMemset(queues)");
+    HIP_OR_FAIL(t->alloc(&aux, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMalloc(aux)");
+    HIP_OR_FAIL(hipMemset(aux, 0, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMemset(aux)");
+    for (int b = 0; b < 2; ++b) {
+        HIP_OR_FAIL(t->alloc(&t->stage[b], (size_t)(order + 1) * (t->stage_len + 4) * 4), "hipMalloc(staging)");
+        HIP_OR_FAIL(hipMemset(t->stage[b], 0, (size_t)(order + 1) * (t->stage_len + 4) * 4), "hipMemset(staging)");
+        HIP_OR_FAIL(hipEventCreateWithFlags(&t->copied[b], hipEventDisableTiming), "hipEventCreate");
+        HIP_OR_FAIL(hipEventCreateWithFlags(&t->consumed[b], hipEventDisableTiming), "hipEventCreate");
+    }
+    HIP_OR_FAIL(hipEventCreateWithFlags(&t->call_start, hipEventDisableTiming), "hipEventCreate");
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&t->copy_stream, hipStreamNonBlocking), "hipStreamCreate");
+    try {
+        const std::vector<int32_t> lex = amped::lex_order(order, t->dims, nnz, indices);
+        const size_t padded = ((size_t)nnz + 4) * 4;
+        for (int d = 0; d < order; ++d) {
+            HostModeLayout lay;
+            amped::mode_order(t->dims, nnz, indices, lex, d, lay.perm);
+            amped::mode_tables(t->dims, nnz, indices, d, t->chunk, lay);
+            auto& h = t->hmode[d];
+            HIP_OR_FAIL(t->host_alloc(&p, padded), "hipHostMalloc(out_idx)");
+            h.out_idx = static_cast<int32_t*>(p);
+            amped::gather_i32(indices + (int64_t)d * nnz, lay.perm.data(), 0, nnz, h.out_idx);
+            int j = 0;
+            for (int w = 0; w < order; ++w) {
+                if (w == d) continue;
+                HIP_OR_FAIL(t->host_alloc(&p, padded), "hipHostMalloc(in_idx)");
+                h.in_idx[j] = static_cast<int32_t*>(p);
+                amped::gather_i32(indices + (int64_t)w * nnz, lay.perm.data(), 0, nnz, h.in_idx[j++]);
+            }
+            HIP_OR_FAIL(t->host_alloc(&p, padded), "hipHostMalloc(values)");
+            h.val = static_cast<float*>(p);
+            amped::gather_f32(values, lay.perm.data(), 0, nnz, h.val);
+            for (int k = 0; k < 4; ++k) {
+                h.out_idx[nnz + k] = 0;
+                for (int jj = 0; jj < order - 1; ++jj) h.in_idx[jj][nnz + k] = 0;
+                h.val[nnz + k] = 0.f;
+            }
+            st = upload_tables(t, t->mode[d], d, lay, queues, aux);
+            if (st != AMPED_OK) return st;
+            if (t->keep_perm) t->hperm[d] = std::move(lay.perm);
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(AMPED_ERR_NOMEM, "host allocation failed");
+    }
+    t->loss_dev = t->mode[0];
+    t->loss_dev.queue = static_cast<int*>(queues) + order;
+cleanup:
+    return st;
+}
+
+// Streams mode d's host-resident layout through the device: shard i goes to
+// staging buffer i % 2 on the copy stream, stream s waits for it, runs
+// fn(shard, i) and marks the buffer free again, so the copy of shard i+1
+// overlaps the kernels of shard i.  cut(start) is a shard's end (at most
+// stage_len nonzeros past start).  The shard's ModeDev points at the staging
+// arrays, carries the output indices on both sides of it, and only the
+// first shard's init zeroes rows.
+template <typename Cut, typename Fn>
+amped_status stream_shards(amped_tensor_s* t, int d, const ModeDev& base, hipStream_t s, Cut&& cut, Fn&& fn)
+{
+    const int order = t->order;
+    const int64_t nnz = t->nnz;
+    const auto& h = t->hmode[d];
+    if (nnz == 0) return fn(base, 0);
+    hipError_t e;
+    // the staging buffers may still be read by earlier work on s
+    if ((e = hipEventRecord(t->call_start, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(t->copy_stream, t->call_start, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent");
+    const size_t stride = (size_t)t->stage_len + 4;
+    int i = 0;
+    for (int64_t start = 0; start < nnz; ++i) {
+        const int64_t end = cut(start);
+        if (end <= start || end - start > t->stage_len)
+            return fail(AMPED_ERR_UNSUPPORTED, "a run of equal coordinates is longer than a shard (%lld nonzeros)",
+                        (long long)t->stage_len);
+        const int64_t len = end - start;
+        const int b = i & 1;
+        if (i >= 2 && (e = hipStreamWaitEvent(t->copy_stream, t->consumed[b], 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent");
+        int32_t* sb = static_cast<int32_t*>(t->stage[b]);
+        ModeDev m = base;
+        auto put = [&](int slot, const void* src) {
+            return hipMemcpyAsync(sb + slot * stride, static_cast<const int32_t*>(src) + start, (size_t)len * 4,
+                                  hipMemcpyHostToDevice, t->copy_stream);
+        };
+        if ((e = put(0, h.out_idx)) != hipSuccess) return hip_fail(e, "hipMemcpyAsync(shard)");
+        m.out_idx = sb;
+        for (int j = 0; j < order - 1; ++j) {
+            if ((e = put(1 + j, h.in_idx[j])) != hipSuccess) return hip_fail(e, "hipMemcpyAsync(shard)");
+            m.in_idx[j] = sb + (1 + j) * stride;
+        }
+        if ((e = put(order, h.val)) != hipSuccess) return hip_fail(e, "hipMemcpyAsync(shard)");
+        m.val = reinterpret_cast<const float*>(sb + order * stride);
+        if ((e = hipEventRecord(t->copied[b], t->copy_stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipStreamWaitEvent(s, t->copied[b], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        m.nnz = len;
+        m.n_chunks = (len + t->chunk - 1) / t->chunk;
+        m.prev_key = start > 0 ? h.out_idx[start - 1] : -1;
+        m.next_key = end < nnz ? h.out_idx[end] : -1;
+        if (i > 0) {
+            m.n_zero = 0;
+            m.n_gaps = 0;
+        }
+        amped_status st = fn(m, i);
+        if (st != AMPED_OK) return st;
+        if ((e = hipEventRecord(t->consumed[b], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        start = end;
+    }
+    return AMPED_OK;
+}
+
+// Shard ends for the MTTKRP-shaped kernels: whole chunks, stage_len each.
+struct ChunkCut {
+    int64_t nnz, len;
+    int64_t operator()(int64_t start) const { return std::min(start + len, nnz); }
+};
+
 }  // namespace
 
 extern "C" {
@@ -208,10 +408,14 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     *out = nullptr;
     amped_status st = validate_coo(order, dims, nnz, indices, values);
     if (st != AMPED_OK) return st;
-    int64_t chunk = amped::kDefaultChunk, cap = 0;
-    bool keep_perm = false;
+    int64_t chunk = amped::kDefaultChunk, cap = 0, shard_opt = 0;
+    bool keep_perm = false, host_layout = false;
     if (opts) {
-        if (opts->reserved != 0) return fail(AMPED_ERR_INVALID, "options.reserved must be 0");
+        if (opts->host_layout != 0 && opts->host_layout != 1)
+            return fail(AMPED_ERR_INVALID, "host_layout must be 0 or 1");
+        host_layout = opts->host_layout == 1;
+        if (opts->shard_nnz < 0) return fail(AMPED_ERR_INVALID, "shard_nnz < 0");
+        shard_opt = opts->shard_nnz;
         if (opts->chunk_nnz < 0 || opts->chunk_nnz > amped::kMaxChunk)
             return fail(AMPED_ERR_INVALID, "chunk_nnz %lld outside [0, 2^28]", (long long)opts->chunk_nnz);
         if (opts->chunk_nnz > 0) chunk = opts->chunk_nnz;
@@ -228,8 +432,18 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     for (int d = 0; d < order; ++d) row_bytes += 4 * dims[d] + 4 * amped::kHotTableLen;
     // device sort: lexicographic order, key and value ping-pong buffers, scratch
     const int64_t sort_bytes = 16 * nnz + 4 * amped::sort_scratch_words(nnz);
-    const int64_t peak = layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
-                         4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8 + row_bytes + sort_bytes + 4096;
+    // host-resident layouts: two shard buffers of whole chunks instead
+    const int64_t n_chunks = (nnz + chunk - 1) / chunk;
+    const int64_t shard_chunks =
+        std::max<int64_t>(1, std::min(((shard_opt > 0 ? shard_opt : (int64_t)1 << 25) + chunk - 1) / chunk,
+                                      std::max<int64_t>(n_chunks, 1)));
+    const int64_t stage_len = shard_chunks * chunk;
+    if (host_layout && stage_len > 0x7FFFFFFF - 4)
+        return fail(AMPED_ERR_INVALID, "shard of %lld nonzeros too large", (long long)stage_len);
+    const int64_t peak =
+        host_layout ? 2 * (int64_t)(order + 1) * 4 * (stage_len + 4) + row_bytes + 4096
+                    : layout_bytes + (keep_perm ? (int64_t)order * 4 * nnz : 0) + (int64_t)(order + 1) * 4 * nnz +
+                          4 * nnz + (int64_t)order * ((nnz + chunk - 1) / chunk + 64) * 8 + row_bytes + sort_bytes + 4096;
     if (cap > 0 && peak > cap)
         return fail(AMPED_ERR_NOMEM, "layouts need up to %lld device bytes, cap is %lld", (long long)peak,
                     (long long)cap);
@@ -246,6 +460,19 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
     t->n_chunks = (nnz + chunk - 1) / chunk;
     t->device = dev;
     t->keep_perm = keep_perm;
+    if (host_layout) {
+        t->host_layout = true;
+        t->stage_len = stage_len;
+        st = build_host_layout(t, indices, values);
+        if (st != AMPED_OK) {
+            (void)hipDeviceSynchronize();
+            t->free_all();
+            delete t;
+            return st;
+        }
+        *out = t;
+        return AMPED_OK;
+    }
 
     hipStream_t stream = nullptr;
     void* d_cols[kMaxOrder] = {};
@@ -343,32 +570,8 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             m.val = static_cast<float*>(p);
             HIP_OR_FAIL(hipStreamSynchronize(stream), "layout build");
             amped::mode_tables_sorted(keys_h.data(), nnz, dims[d], chunk, lay);
-            if (!lay.zero_rows.empty()) {
-                HIP_OR_FAIL(t->alloc(&p, lay.zero_rows.size() * 4), "hipMalloc(zero rows)");
-                HIP_OR_FAIL(hipMemcpy(p, lay.zero_rows.data(), lay.zero_rows.size() * 4, hipMemcpyHostToDevice),
-                            "hipMemcpy(zero rows)");
-                m.zero_rows = static_cast<int32_t*>(p);
-            }
-            HIP_OR_FAIL(t->alloc(&p, lay.hot.size() * 4), "hipMalloc(hot rows)");
-            HIP_OR_FAIL(hipMemcpy(p, lay.hot.data(), lay.hot.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(hot rows)");
-            m.hot = static_cast<int32_t*>(p);
-            if (!lay.gaps.empty()) {
-                HIP_OR_FAIL(t->alloc(&p, lay.gaps.size() * 4), "hipMalloc(gaps)");
-                HIP_OR_FAIL(hipMemcpy(p, lay.gaps.data(), lay.gaps.size() * 4, hipMemcpyHostToDevice),
-                            "hipMemcpy(gaps)");
-                m.gaps = static_cast<int32_t*>(p);
-            }
-            m.nnz = nnz;
-            m.chunk = chunk;
-            m.n_chunks = t->n_chunks;
-            m.rows = dims[d];
-            m.n_zero = (int64_t)lay.zero_rows.size();
-            m.zero_row = d_aux;
-            m.sink = static_cast<float*>(d_aux) + 4;
-            m.n_gaps = (int64_t)lay.gaps.size() / 2;
-            m.queue = static_cast<int*>(d_queues) + d;
-            t->flags[d] = std::move(lay.flags);
-            t->touched[d] = lay.touched;
+            st = upload_tables(t, m, d, lay, d_queues, d_aux);
+            if (st != AMPED_OK) goto cleanup;
         }
         t->loss_dev = t->mode[0];
         t->loss_dev.queue = static_cast<int*>(d_queues) + order;
@@ -449,7 +652,16 @@ amped_status amped_tensor_layout(amped_tensor_t t, int mode, int32_t* perm, int3
     const ModeDev& m = t->mode[mode];
     const size_t bytes = (size_t)t->nnz * 4;
     amped_status st = AMPED_OK;
-    if (bytes) {
+    if (t->host_layout) {
+        const auto& h = t->hmode[mode];
+        if (bytes) {
+            if (perm) std::memcpy(perm, t->hperm[mode].data(), bytes);
+            if (out_idx) std::memcpy(out_idx, h.out_idx, bytes);
+            if (in_idx)
+                for (int j = 0; j < t->order - 1; ++j) std::memcpy(in_idx + (int64_t)j * t->nnz, h.in_idx[j], bytes);
+            if (values) std::memcpy(values, h.val, bytes);
+        }
+    } else if (bytes) {
         if (perm) HIP_OR_FAIL(hipMemcpy(perm, t->perm[mode], bytes, hipMemcpyDeviceToHost), "hipMemcpy(perm)");
         if (out_idx) HIP_OR_FAIL(hipMemcpy(out_idx, m.out_idx, bytes, hipMemcpyDeviceToHost), "hipMemcpy(out_idx)");
         if (in_idx)
@@ -508,9 +720,13 @@ amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const*
     a.scale = scale;
     a.out = out;
     a.stream = static_cast<hipStream_t>(stream);
-    hipError_t e = amped::launch_mttkrp(a);
-    if (e != hipSuccess) return hip_fail(e, grad ? "amped_cp_grad" : "amped_mttkrp");
-    return AMPED_OK;
+    auto launch = [&](const ModeDev& m, int) -> amped_status {
+        a.m = &m;
+        hipError_t e = amped::launch_mttkrp(a);
+        return e == hipSuccess ? AMPED_OK : hip_fail(e, grad ? "amped_cp_grad" : "amped_mttkrp");
+    };
+    if (t->host_layout) return stream_shards(t, mode, t->mode[mode], a.stream, ChunkCut{t->nnz, t->stage_len}, launch);
+    return launch(t->mode[mode], 0);
 }
 
 }  // namespace
@@ -610,8 +826,31 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
         w.rank = rank;
     }
     if (!w.have_xnorm2) {
-        if ((e = amped::launch_tensor_norm2(t->mode[0], N - 1, w.xnorm2, s)) != hipSuccess)
-            return hip_fail(e, "tensor norm");
+        auto norm = [&](const ModeDev& m, int i) -> amped_status {
+            hipError_t en = amped::launch_tensor_norm2(m, N - 1, w.xnorm2, i > 0, s);
+            return en == hipSuccess ? AMPED_OK : hip_fail(en, "tensor norm");
+        };
+        if (t->host_layout) {
+            // shards end between runs of equal coordinates (each run is summed
+            // before squaring)
+            const auto& h = t->hmode[0];
+            auto same = [&](int64_t p, int64_t q) {
+                if (h.out_idx[p] != h.out_idx[q]) return false;
+                for (int j = 0; j < N - 1; ++j)
+                    if (h.in_idx[j][p] != h.in_idx[j][q]) return false;
+                return true;
+            };
+            auto cut = [&](int64_t start) {
+                int64_t end = std::min(start + t->stage_len, t->nnz);
+                if (end < t->nnz)
+                    while (end > start && same(end - 1, end)) --end;
+                return end;
+            };
+            st = stream_shards(t, 0, t->mode[0], s, cut, norm);
+        } else {
+            st = norm(t->mode[0], 0);
+        }
+        if (st != AMPED_OK) return st;
         w.have_xnorm2 = true;
     }
     w.have_grams = false;   // stays false if the sweep stops part-way
@@ -655,9 +894,14 @@ amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* facto
     }
     a.loss = loss;
     a.stream = static_cast<hipStream_t>(stream);
-    hipError_t e = amped::launch_cp_loss(a);
-    if (e != hipSuccess) return hip_fail(e, "amped_cp_loss");
-    return AMPED_OK;
+    auto launch = [&](const ModeDev& m, int i) -> amped_status {
+        a.m = &m;
+        a.accumulate = i > 0;
+        hipError_t e = amped::launch_cp_loss(a);
+        return e == hipSuccess ? AMPED_OK : hip_fail(e, "amped_cp_loss");
+    };
+    if (t->host_layout) return stream_shards(t, 0, t->loss_dev, a.stream, ChunkCut{t->nnz, t->stage_len}, launch);
+    return launch(t->loss_dev, 0);
 }
 
 }  // extern "C"

@@ -84,6 +84,11 @@ struct ModeDev {
     const int32_t* hot = nullptr;                  // hot-row tables of this mode [kHotTableLen]
     const void* zero_row = nullptr;                // 16 zero bytes
     float* sink = nullptr;                         // kSinkFloats floats of write-only scratch
+    // A shard of a longer layout (whole chunks of it): the output indices just
+    // before and after the shard, -1 at the layout's ends.  Rows that cross a
+    // shard edge cross a chunk edge, so they are in the zero-row list and every
+    // shard adds into them.
+    int prev_key = -1, next_key = -1;
 };
 
 enum class FactorType { F32 = 0, BF16 = 1 };
@@ -120,6 +125,7 @@ struct LossArgs {
     int64_t in_rows[kMaxOrder - 1] = {};
     const int32_t* in_hot[kMaxOrder - 1] = {};
     double* loss = nullptr;
+    bool accumulate = false;                       // add to *loss instead of resetting it
     hipStream_t stream = nullptr;
 };
 hipError_t launch_cp_loss(const LossArgs& a);
@@ -134,8 +140,9 @@ hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, dou
                             double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st);
 // A = M W (rows x R, W R x R), fp32.
 hipError_t launch_als_solve(const float* M, const float* W, float* A, int64_t rows, int R, hipStream_t st);
-// ||X||^2 over a layout whose exact duplicates are adjacent.
-hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, hipStream_t st);
+// ||X||^2 over a layout whose exact duplicates are adjacent (accumulate: add
+// to *result; no run of duplicates may cross the layout's ends then).
+hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, bool accumulate, hipStream_t st);
 
 // dst[p] = src[perm[p]] for p < n, 32-bit words, on the device.
 hipError_t launch_permute32(void* dst, const void* src, const int32_t* perm, int64_t n, hipStream_t st);

@@ -114,6 +114,8 @@ struct KParams {
     uint32_t own_bytes;
     const void* zero_row;     // 16 zero bytes: what padding entries read on the 64-bit path
     float* sink;              // 64 * 8 floats that absorb stores which must not land
+    int prev_key;             // output index just before position 0 of these arrays (-1: none)
+    int next_key;             // output index just after position nnz - 1 (-1: none)
     const int32_t* hot[kMaxIn];  // per input: direct-mapped table of hot_k rows kept in LDS
     int hot_k;                // LDS row-cache slots per input (power of two; 0 = none)
 };
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         if constexpr (OUT) {
             if (gon) {
                 const int first = p.out_idx[gs];
-                const int prev = gs > 0 ? p.out_idx[gs - 1] : -1;
+                const int prev = gs > 0 ? p.out_idx[gs - 1] : p.prev_key;
                 last_key = p.out_idx[ge - 1];
                 lsh = (prev == first) ? 1 : 0;
                 open_key = first;
@@ -739,7 +741,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         // end of the run: the open row
         bool parked = false;
         if (gon) {
-            const int nextk = ge < p.nnz ? p.out_idx[ge] : -1;
+            const int nextk = ge < p.nnz ? p.out_idx[ge] : p.next_key;
             const bool right_shared = (nextk == open_key);
             const bool left_open = first_open && lsh;  // the run is one row, continued from the left
             if (left_open && s == 0) s_key[wv][2 * g] = -1;

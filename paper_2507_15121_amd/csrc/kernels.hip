@@ -183,6 +183,8 @@ KParams base_params(const ModeDev& m)
     k.rows = m.rows;
     k.zero_row = m.zero_row;
     k.sink = m.sink;
+    k.prev_key = m.prev_key;
+    k.next_key = m.next_key;
     return k;
 }
 
@@ -283,7 +285,7 @@ hipError_t launch_cp_loss(const LossArgs& a)
     k.ld = a.rank;
     k.col0 = 0;
     k.ncols = a.rank;
-    hipError_t e = launch_init(m, nullptr, 0, 0, 0, a.loss, a.stream);
+    hipError_t e = launch_init(m, nullptr, 0, 0, 0, a.accumulate ? nullptr : a.loss, a.stream);
     if (e != hipSuccess) return e;
     if (m.n_chunks == 0) return hipSuccess;
     const int block = mttkrp_block(2);

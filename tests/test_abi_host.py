@@ -113,16 +113,18 @@ def test_create_argument_errors():
     assert _create_status(3, [4, 4, 4], -1, ip, vp) == api.ERR_INVALID
     assert _create_status(3, [4, 4, 4], 4, None, vp) == api.ERR_INVALID
     assert _create_status(3, [4, 4, 4], 4, ip, None) == api.ERR_INVALID
-    assert _create_status(3, [4, 4, 4], 4, ip, vp, (-5, 0, 0, 0)) == api.ERR_INVALID
-    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 0, 2, 0)) == api.ERR_INVALID
-    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 0, 0, 1)) == api.ERR_INVALID
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (-5, 0, 0, 0, 0)) == api.ERR_INVALID
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 0, 2, 0, 0)) == api.ERR_INVALID
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 0, 0, 2, 0)) == api.ERR_INVALID
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 0, 0, 1, -1)) == api.ERR_INVALID
     bad = idx.copy()
     bad[1, 2] = 4
     assert _create_status(3, [4, 4, 4], 4, bad.ctypes.data, vp) == api.ERR_RANGE
     bad[1, 2] = -1
     assert _create_status(3, [4, 4, 4], 4, bad.ctypes.data, vp) == api.ERR_RANGE
     # device byte cap: refused before the device is touched
-    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 64, 0, 0)) == api.ERR_NOMEM
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 64, 0, 0, 0)) == api.ERR_NOMEM
+    assert _create_status(3, [4, 4, 4], 4, ip, vp, (0, 64, 0, 1, 0)) == api.ERR_NOMEM
     L = api.lib()
     assert L.amped_tensor_create(3, np.array([4, 4, 4], np.int64).ctypes.data, 4, ip, vp, None,
                                  None) == api.ERR_INVALID
@@ -154,3 +156,21 @@ def test_create_without_gpu_reports_unsupported():
     idx = np.zeros((3, 4), np.int32)
     val = np.zeros(4, np.float32)
     assert _create_status(3, [4, 4, 4], 4, idx.ctypes.data, val.ctypes.data) == api.ERR_UNSUPPORTED
+
+
+def test_host_layout_needs_only_two_shards_of_device_memory():
+    """A byte cap that refuses the device-resident layouts of 100k nonzeros
+    (about 5 MB) admits the same tensor with host-resident layouts streamed in
+    8192-nonzero shards (two staging buffers of about 130 KB); without a GPU
+    the call then stops at the device check."""
+    rng = np.random.default_rng(3)
+    nnz = 100_000
+    dims = [500, 400, 300]
+    idx = np.stack([rng.integers(0, d, nnz) for d in dims]).astype(np.int32)
+    val = rng.random(nnz, dtype=np.float32)
+    ip, vp = idx.ctypes.data, val.ctypes.data
+    cap = 1 << 20
+    assert _create_status(3, dims, nnz, ip, vp, (0, cap, 0, 0, 0)) == api.ERR_NOMEM
+    assert _create_status(3, dims, nnz, ip, vp, (0, cap, 0, 1, 8192)) in (api.OK, api.ERR_UNSUPPORTED)
+    # the default shard (2^25 nonzeros) is clipped to the tensor: one chunk-rounded shard
+    assert _create_status(3, dims, nnz, ip, vp, (0, cap, 0, 1, 0)) == api.ERR_NOMEM
