@@ -59,13 +59,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and CP loss/grad forms")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--out-of-core", action="store_true",
-                    help="also time the all-mode fp32 step with host-resident layouts streamed in shards")
+    ap.add_argument("--no-out-of-core", action="store_true",
+                    help="skip timing the all-mode fp32 step with host-resident layouts streamed in shards")
     ap.add_argument("--shard-nnz", type=int, default=0, help="nonzeros per streamed shard (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     return ap.parse_args()
+
+
+def slice_stats(st):
+    """Per mode: distinct indices, and the shares of nonzeros in the largest
+    slice and in the 10 largest slices."""
+    out = {"distinct": [], "largest_slice_share": [], "top10_slice_share": []}
+    for w in range(st.order):
+        c = np.bincount(st.idx[w], minlength=st.dims[w])
+        top = np.partition(c, -10)[-10:] if c.size >= 10 else c
+        out["distinct"].append(int(np.count_nonzero(c)))
+        out["largest_slice_share"].append(float(top.max()) / max(st.nnz, 1))
+        out["top10_slice_share"].append(float(top.sum()) / max(st.nnz, 1))
+    return out
 
 
 def sampled_rel_errors(st, factors64, outs, rank, rng, n_rows=200):
@@ -117,6 +130,8 @@ def main():
     factors = synth.factors(st.dims, R, seed=seed)
     gen_s = time.time() - t0
     log("generated %s nnz=%d in %.1fs (%s)" % (wl.name, st.nnz, gen_s, st.info))
+    index_stats = slice_stats(st)
+    log("index stats %s" % index_stats)
 
     t0 = time.time()
     T = api.Tensor(st.idx, st.val, st.dims, chunk_nnz=args.chunk)
@@ -255,7 +270,7 @@ def main():
             log("cp-als sweep: %s" % forms["cp_als_sweep"])
             del als_fac
 
-    if args.out_of_core:
+    if not args.no_out_of_core:
         # host-resident layouts (pinned host memory, host order builder),
         # streamed to the device in shards on every call
         t0 = time.time()
@@ -357,7 +372,7 @@ def main():
         "per_mode": per_mode,
         "forms": forms,
         "accuracy": acc,
-        "layout_build_s": build_s, "generate_s": gen_s,
+        "layout_build_s": build_s, "generate_s": gen_s, "index_stats": index_stats,
         "cpu_baseline": cpu,
     }
     T.close()
