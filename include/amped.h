@@ -215,8 +215,8 @@ amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void 
  * and after the last mode the fit 1 - ||X - Xhat|| / ||X|| of the CP model
  * Xhat = sum_r lambda_r a_r o b_r o ... to the full tensor (entries not
  * stored are zeros; exact duplicates add up).  The R x R algebra runs in
- * fp64 (Cholesky factor of V; a non-positive pivot is replaced by a tiny
- * one), the row-sized products in fp32.  The fit comes from
+ * fp64 (V^{-1} by Gauss-Jordan elimination; a non-positive pivot is replaced
+ * by a tiny one), the row-sized products in fp32.  The fit comes from
  * ||X||^2 - 2<X, Xhat> + ||Xhat||^2, so with fp32 products its absolute error
  * is about 1e-6 / (1 - fit), at most about 2e-3 as the fit nears 1.
  *   factors  host array of `order` DEVICE pointers, each dims[w] x rank fp32,

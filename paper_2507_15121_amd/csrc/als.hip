@@ -18,7 +18,7 @@
 //    supplying A[row0 + l/32][tile*32 + l%32] as both operands (the K index of
 //    the product is the row).  Per-slab fp32 partials are summed in fp64 by
 //    gram_reduce, in slab order (deterministic).
-//  * als_small: one block, fp64: V, its Cholesky factor, V^{-1}, P, lambda,
+//  * als_small: one block, fp64: V, V^{-1} (Gauss-Jordan), P, lambda,
 //    the new G_d, W (fp32) and, after the last mode, the fit.
 //  * als_solve: A_d = M W, 64 rows per block staged through LDS with W.
 //  * tensor_norm2: ||X||^2 over the mode-0 layout, exact duplicates (adjacent
@@ -162,8 +162,18 @@ __global__ void __launch_bounds__(256) gram_reduce(const float* partial, int64_t
     const int e = blockIdx.x * 32 + e32;
     const int RR = R * R;
     double acc = 0.0;
-    if (e < RR)
-        for (int64_t k = sl; k < nslab; k += 8) acc += (double)partial[k * RR + e];
+    if (e < RR) {
+        // 8 loads in flight, added in slab order
+        int64_t k = sl;
+        for (; k + 56 < nslab; k += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(k + 8 * u) * RR + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += (double)v[u];
+        }
+        for (; k < nslab; k += 8) acc += (double)partial[k * RR + e];
+    }
     s[sl][e32] = acc;
     __syncthreads();
     if (sl == 0 && e < RR) {
@@ -196,41 +206,39 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
         L[e] = 0.0;
     }
     __syncthreads();
-    // Cholesky V = L L^T, column by column; a pivot that is not positive
-    // (V singular, e.g. a zero factor column) is replaced by a tiny one
+    // V^{-1} by Gauss-Jordan elimination without pivoting (V is symmetric
+    // positive semi-definite): L holds the reduced V, Vi starts as I.  A pivot
+    // that is not positive (V singular, e.g. a zero factor column) is replaced
+    // by a tiny one, so that row and column of V^{-1} stay apart from the rest.
     double vmax = 0.0;
     for (int k = 0; k < R; ++k) vmax = fmax(vmax, fabs(V[k * R + k]));
     const double tiny = (vmax > 0.0 ? vmax : 1.0) * 1e-30;
-    __shared__ double piv;
-    for (int k = 0; k < R; ++k) {
-        if (tid == 0) {
-            double s = V[k * R + k];
-            for (int j = 0; j < k; ++j) s -= L[k * R + j] * L[k * R + j];
-            piv = sqrt(s > tiny ? s : tiny);
-            L[k * R + k] = piv;
-        }
-        __syncthreads();
-        for (int i = k + 1 + tid; i < R; i += 256) {
-            double s = V[i * R + k];
-            for (int j = 0; j < k; ++j) s -= L[i * R + j] * L[k * R + j];
-            L[i * R + k] = s / piv;
-        }
-        __syncthreads();
-    }
-    // V^{-1}: column c solves L y = e_c, then L^T x = y (in place)
-    for (int c = tid; c < R; c += 256) {
-        for (int i = 0; i < R; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int j = 0; j < i; ++j) s -= L[i * R + j] * Vi[j * R + c];
-            Vi[i * R + c] = s / L[i * R + i];
-        }
-        for (int i = R - 1; i >= 0; --i) {
-            double s = Vi[i * R + c];
-            for (int j = i + 1; j < R; ++j) s -= L[j * R + i] * Vi[j * R + c];
-            Vi[i * R + c] = s / L[i * R + i];
-        }
+    __shared__ double fcol[128];
+    for (int e = tid; e < RR; e += 256) {
+        L[e] = V[e];
+        Vi[e] = (e / R == e % R) ? 1.0 : 0.0;
     }
     __syncthreads();
+    for (int k = 0; k < R; ++k) {
+        // pivot row k scaled by 1/pivot; the column-k multipliers saved first
+        const double pv = L[k * R + k];
+        const double inv = 1.0 / (pv > tiny ? pv : tiny);
+        for (int i = tid; i < R; i += 256) fcol[i] = L[i * R + k];
+        __syncthreads();
+        for (int j = tid; j < R; j += 256) {
+            L[k * R + j] *= inv;
+            Vi[k * R + j] *= inv;
+        }
+        __syncthreads();
+        for (int e = tid; e < RR; e += 256) {
+            const int i = e / R, j = e % R;
+            if (i == k) continue;
+            const double f = fcol[i];
+            L[e] -= f * L[k * R + j];
+            Vi[e] -= f * Vi[k * R + j];
+        }
+        __syncthreads();
+    }
     // S into V's slot (V is no longer needed), then T = S V^{-1}
     for (int e = tid; e < RR; e += 256) V[e] = S[e];
     __syncthreads();
@@ -310,12 +318,26 @@ __global__ void __launch_bounds__(256) als_solve(const float* M, const float* W,
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int nr = (int)std::min<int64_t>(RB, rows - r0);
     if ((R & 3) == 0) {
+        // 8 loads per thread in flight before their LDS stores (a full block is
+        // exactly 8 float4 per thread when R is a multiple of 8)
         const float4* M4 = reinterpret_cast<const float4*>(M + r0 * R);
-        for (int e = tid; e < nr * R / 4; e += 256) {
-            const float4 v = M4[e];
-            const int i = (4 * e) / R, k = (4 * e) % R;
-            float* d = &sM[i * (R + 1) + k];
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        const int n4 = nr * R / 4;
+        for (int base = 0; base < n4; base += 8 * 256) {
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                v[u] = e < n4 ? M4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                if (e < n4) {
+                    const int i = (4 * e) / R, k = (4 * e) % R;
+                    float* d = &sM[i * (R + 1) + k];
+                    d[0] = v[u].x; d[1] = v[u].y; d[2] = v[u].z; d[3] = v[u].w;
+                }
+            }
         }
     } else {
         for (int e = tid; e < nr * R; e += 256) sM[(e / R) * (R + 1) + e % R] = M[r0 * R + e];
@@ -388,7 +410,11 @@ __global__ void __launch_bounds__(256) tensor_norm2(const int32_t* out_idx, InId
 
 int64_t gram_slabs(int64_t rows)
 {
-    return std::max<int64_t>(1, std::min<int64_t>((rows + 8191) / 8192, 2048));
+    // about 8192 rows per slab; above 256 slabs a multiple of 256, so every
+    // CU of the 256 gets the same number of slabs
+    int64_t n = (rows + 8191) / 8192;
+    if (n > 256) n = (n + 255) / 256 * 256;
+    return std::max<int64_t>(1, std::min<int64_t>(n, 2048));
 }
 
 hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st)
