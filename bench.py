@@ -235,6 +235,25 @@ def main():
         ms_cp = a.elapsed_time(b) / args.steps
         forms["cp_loss_and_grad"] = {"ms_per_step": ms_cp, "loss": float(loss),
                                      "nnz_per_s": (N + 1) * st.nnz / (ms_cp * 1e-3)}
+        # directional finite difference at full size: [L(A + eps V) - L(A - eps V)] / (2 eps)
+        # against <grad L, V> for a seeded random direction V (losses summed in fp64)
+        gen = torch.Generator(device="cuda").manual_seed(1234)
+        Vd = [torch.rand(f.shape, generator=gen, device="cuda") * 2 - 1 for f in dfac]
+        def dot64(x, y, chunk=1 << 24):   # float64 inner product in chunks (bounded temporaries)
+            x, y = x.reshape(-1), y.reshape(-1)
+            return sum(float((x[i:i + chunk].double() * y[i:i + chunk].double()).sum())
+                       for i in range(0, x.numel(), chunk))
+        dirderiv = sum(dot64(grads[d], Vd[d]) for d in range(N))
+        eps = 1e-3
+        lp = torch.empty((), dtype=torch.float64, device="cuda")
+        lm = torch.empty((), dtype=torch.float64, device="cuda")
+        api.cp_loss(T, [f + eps * v for f, v in zip(dfac, Vd)], out=lp, stream=stream)
+        api.cp_loss(T, [f - eps * v for f, v in zip(dfac, Vd)], out=lm, stream=stream)
+        torch.cuda.synchronize()
+        fd = (float(lp) - float(lm)) / (2 * eps)
+        forms["cp_loss_and_grad"]["fd_check"] = {"directional_derivative": dirderiv, "central_difference": fd,
+                                                 "eps": eps, "rel_diff": abs(fd - dirderiv) / abs(dirderiv)}
+        del Vd
         log("cp loss+grad: %s" % forms["cp_loss_and_grad"])
         if R <= 128:
             # CP-ALS sweeps (MTTKRP + Gram + R x R algebra + update per mode)

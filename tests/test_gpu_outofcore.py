@@ -165,3 +165,21 @@ def test_streamed_empty_tensor_zeroes_outputs():
         assert not hip_mttkrp(t, d, dfac).any()
     assert float(api.cp_loss(t, dfac)) == 0.0
     t.close()
+
+
+@pytest.mark.parametrize("dims,rank", [((40, 30), 32), ((12, 10, 8, 6, 5), 16), ((6, 5, 5, 4, 4, 3, 3, 2), 4)])
+def test_streamed_orders_2_5_8(dims, rank):
+    rng = np.random.default_rng(len(dims) + 40)
+    nnz = min(2000, int(np.prod(dims)) // 2)
+    idx, _ = synth.coords(dims, nnz, "uniform", seed=len(dims) + 40)
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [rng.uniform(-1, 1, (d, rank)).astype(np.float32) for d in dims]
+    t = api.Tensor(idx, val, dims, chunk_nnz=16, host_layout=True, shard_nnz=48)
+    dfac = dev_factors(factors)
+    for d in range(len(dims)):
+        e = rel(hip_mttkrp(t, d, dfac), oracle_mttkrp(idx, val, dims, factors, d))
+        assert e <= 1e-5, "order %d mode %d rel %.2e" % (len(dims), d, e)
+    loss = float(api.cp_loss(t, dfac))
+    ref_loss, _ = oracle.cp_loss(idx, val, factors)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    t.close()
