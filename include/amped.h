@@ -30,7 +30,10 @@
  *  - A tensor handle is immutable after creation and binds the HIP device that
  *    was current at creation.  It owns a small device work queue per mode, so
  *    calls that use the same handle AND the same mode (or two cp_loss calls)
- *    must be ordered on one stream; calls on different modes may overlap.
+ *    must be ordered on one stream; calls on different modes may overlap,
+ *    except on a handle with host-resident layouts (options.host_layout),
+ *    whose calls share its shard buffers and must all be ordered on one
+ *    stream.  amped_cp_als_sweep calls on one handle must not overlap.
  *  - Limits: 2 <= order <= 8; 1 <= dims[w] <= 2^31-1; 0 <= nnz <= 2^31-1;
  *    1 <= rank <= 4096.
  */
@@ -62,7 +65,8 @@ typedef struct {
     int64_t device_byte_cap;  /* 0 = no cap; otherwise creation fails with NOMEM,
                                  before touching the device, if the layouts would
                                  need more device bytes than this.                     */
-    int32_t keep_perm;        /* 1 = keep each mode's permutation on the device so
+    int32_t keep_perm;        /* 1 = keep each mode's permutation (on the device, or
+                                 in host memory with host_layout) so
                                  amped_tensor_layout can return it.                    */
     int32_t host_layout;      /* 1 = keep the per-mode layouts in pinned host memory
                                  (built by the host order builder) and stream them to
@@ -95,8 +99,8 @@ typedef struct {
  *   out      host, receives the handle (set to NULL on failure)
  *
  * The orders are computed on the device (stable radix sorts; the same order
- * amped_layout_host computes on the host).  The host arrays are only read
- * during the call.  Errors: INVALID for bad arguments, RANGE for an index
+ * amped_layout_host computes on the host), or on the host with host_layout.
+ * The caller's host arrays are only read during the call.  Errors: INVALID for bad arguments, RANGE for an index
  * outside its mode, NOMEM, HIP, UNSUPPORTED (no device).
  */
 amped_status amped_tensor_create(int order, const int64_t *dims, int64_t nnz,
@@ -117,8 +121,9 @@ amped_status amped_tensor_info(amped_tensor_t t, int *order, int64_t *dims, int6
                                int64_t *device_bytes);
 
 /*
- * Copy mode `mode`'s device layout back to host arrays (introspection and
- * tests; synchronous).  All outputs are nullable:
+ * Copy mode `mode`'s layout (from the device, or from the pinned host copy
+ * with host_layout) to host arrays (introspection and tests; synchronous).
+ * All outputs are nullable:
  *   perm        int32 [nnz]   position -> input nonzero (needs keep_perm=1,
  *                             else INVALID when requested)
  *   out_idx     int32 [nnz]   i_mode in layout order (non-decreasing)
@@ -133,7 +138,8 @@ amped_status amped_tensor_layout(amped_tensor_t t, int mode, int32_t *perm, int3
 
 /*
  * The same per-mode order and chunk flags, computed on the host only (no
- * device involved; same builder as amped_tensor_create).  perm: int32 [nnz];
+ * device involved; the builder amped_tensor_create uses with host_layout, and
+ * the order its device builder produces).  perm: int32 [nnz];
  * chunk_flags: uint8 [ceil(nnz/chunk_nnz)]; either may be NULL.
  */
 amped_status amped_layout_host(int order, const int64_t *dims, int64_t nnz,
@@ -229,7 +235,9 @@ amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void 
  *            if there is no such sweep).  0 otherwise.
  * 1 <= rank <= 128.  The tensor keeps a workspace for the rank of its last
  * sweep (max_d dims[d] x rank floats plus small R x R arrays); sweeps on one
- * tensor must not overlap.
+ * tensor must not overlap.  With host_layout, the one-time ||X||^2 pass is
+ * streamed as well, in shards cut between runs of equal coordinates; a run
+ * longer than a shard returns UNSUPPORTED.
  */
 #define AMPED_ALS_REUSE_GRAMS 1u
 amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float *const *factors, double *lambda,
