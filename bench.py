@@ -373,6 +373,10 @@ def main():
         log("cpu baseline %s" % cpu)
 
     traffic, traffic_src = measured_traffic(wl.name, api.LIB_PATH)
+    # the measured traffic per launch over the mean launch time of this run: the rate the
+    # kernel really moves between L2 and the fabric (Infinity Cache hits included)
+    mean_launch_s = float(np.mean(per_mode_ms)) * 1e-3
+    fabric_gbps = traffic / mean_launch_s / 1e9 if traffic is not None else None
     value = N * st.nnz / (ms_step * 1e-3)
     res = {
         "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
@@ -386,6 +390,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
+                     "traffic_GBps": fabric_gbps,
+                     "traffic_frac": fabric_gbps / HBM_PEAK_GBS if fabric_gbps is not None else None,
                      "kernel": "mttkrp_kernel (fp32)",
                      "bytes_model": "per mode: nnz*(4N+4) + sum_{w!=d} touched_w*R*4 + I_d*R*4"},
         "per_mode": per_mode,
