@@ -166,3 +166,14 @@ def test_reuse_needs_a_previous_sweep_at_that_rank():
         api.cp_als_sweep(t, dG, reuse_grams=True)          # another rank
     torch.cuda.synchronize()
     t.close()
+
+
+@pytest.mark.parametrize("dims,rank", [((3000, 2000), 16), ((300, 250, 200, 150, 40), 8)])
+def test_orders_two_and_five(dims, rank):
+    """Order 2 (V is a single Gram matrix) and order 5 (V the Hadamard of four)."""
+    st = synth.tensor(dims, 20000, "zipf", 1.1, 0.0, seed=len(dims) + 90)
+    (F, lam, fit, Fo, lo, fo), = _sweep_pair(st.idx, st.val, dims, rank, seed=len(dims))
+    errs = [oracle.rel_fro(F[d], Fo[d]) for d in range(len(dims))]
+    log("order %d: errs %s fit %.6f vs %.6f" % (len(dims), ["%.1e" % e for e in errs], fit, fo))
+    assert max(errs) <= 1e-4 and abs(fit - fo) <= 1e-5
+    assert oracle.rel_fro(lam, lo) <= 1e-4
