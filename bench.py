@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and CP loss/grad forms")
-    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the sampled-row checks against the oracle (part of the CPU-baseline leg)")
     ap.add_argument("--no-out-of-core", action="store_true",
                     help="skip timing the all-mode fp32 step with host-resident layouts streamed in shards")
     ap.add_argument("--shard-nnz", type=int, default=0, help="nonzeros per streamed shard (0 = library default)")
@@ -83,7 +84,8 @@ def slice_stats(st):
 
 def sampled_rel_errors(st, factors64, outs, rank, rng, n_rows=200):
     """Relative Frobenius error of each mode's output on sampled rows (the
-    heaviest row plus random touched rows) against the FP64 oracle."""
+    heaviest row plus random touched rows) against the FP64 oracle.  Called
+    from the CPU-baseline leg only."""
     import oracle
     errs = []
     for d, out in enumerate(outs):
@@ -171,11 +173,13 @@ def main():
         end.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        per_mode = [float(np.mean([evs[k][d][0].elapsed_time(evs[k][d][1]) for k in range(args.steps)]))
-                    for d in range(N)]
+        times = [[evs[k][d][0].elapsed_time(evs[k][d][1]) for k in range(args.steps)] for d in range(N)]
+        per_mode = [float(np.mean(x)) for x in times]
+        timed.medians = [float(np.median(x)) for x in times]
         return start.elapsed_time(end) / args.steps, per_mode, wall
 
     ms_step, per_mode_ms, wall = timed(dfac)
+    per_mode_median_ms = timed.medians
     log("fp32: %.3f ms/step, per mode %s ms, wall %.3fs" % (ms_step, ["%.3f" % x for x in per_mode_ms], wall))
 
     # algorithmic bytes per mode: nonzero stream + each distinct input row once + output once
@@ -187,20 +191,11 @@ def main():
     bytes32 = [mode_bytes(d, 4) for d in range(N)]
     achieved = sum(bytes32) / (sum(per_mode_ms) * 1e-3) / 1e9
     per_mode = [{"mode": d, "rows": st.dims[d], "touched": T.touched[d], "ms": per_mode_ms[d],
+                 "ms_median": per_mode_median_ms[d],
                  "nnz_per_s": st.nnz / (per_mode_ms[d] * 1e-3),
                  "algorithmic_GBps": bytes32[d] / (per_mode_ms[d] * 1e-3) / 1e9} for d in range(N)]
 
-    rng = np.random.default_rng(7)
-    factors64 = None
     acc = {}
-    if not args.no_accuracy:
-        factors64 = [f.astype(np.float64) for f in factors]
-        step(dfac)
-        torch.cuda.synchronize()
-        host_outs = [o.cpu().numpy() for o in outs]
-        acc["fp32_rel_err_sampled"] = sampled_rel_errors(st, factors64, host_outs, R, rng)
-        log("fp32 sampled rel errors %s" % acc["fp32_rel_err_sampled"])
-
     forms = {}
     if not args.no_forms:
         dbf = [f.to(torch.bfloat16) for f in dfac]
@@ -209,11 +204,6 @@ def main():
         forms["bf16"] = {"ms_per_step": ms_bf, "per_mode_ms": pm_bf,
                          "nnz_per_s": N * st.nnz / (ms_bf * 1e-3),
                          "algorithmic_GBps": sum(bytes16) / (sum(pm_bf) * 1e-3) / 1e9}
-        if not args.no_accuracy:
-            step(dbf, bf16=True)
-            torch.cuda.synchronize()
-            host_outs = [o.cpu().numpy() for o in outs]
-            forms["bf16"]["rel_err_vs_fp64_sampled"] = sampled_rel_errors(st, factors64, host_outs, R, rng)
         log("bf16: %s" % forms["bf16"])
         # sparse CP loss forward + fused residual/MTTKRP backward for every mode
         grads = [torch.empty_like(f) for f in dfac]
@@ -348,9 +338,32 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the CPU-baseline leg: the only place the bench runs the oracle.  It checks
+        # sampled output rows of the GPU runs, then times the oracle on a sample.
         import oracle
-        if factors64 is None:
-            factors64 = [f.astype(np.float64) for f in factors]
+        factors64 = [f.astype(np.float64) for f in factors]
+        if not args.no_accuracy:
+            step(dfac)
+            torch.cuda.synchronize()
+            host_outs = [o.cpu().numpy() for o in outs]
+            acc["fp32_rel_err_sampled"] = sampled_rel_errors(st, factors64, host_outs, R,
+                                                             np.random.default_rng(7))
+            log("fp32 sampled rel errors %s" % acc["fp32_rel_err_sampled"])
+            if "bf16" in forms:
+                step(dbf, bf16=True)
+                torch.cuda.synchronize()
+                host_outs = [o.cpu().numpy() for o in outs]
+                # against the oracle on the fp32 factors (the bf16 error), and on the
+                # bf16-rounded factors (shows the accumulation stayed fp32); same rows
+                forms["bf16"]["rel_err_vs_fp64_sampled"] = sampled_rel_errors(
+                    st, factors64, host_outs, R, np.random.default_rng(8))
+                rounded = [oracle.bf16_to_f32(oracle.bf16_rne(f)).astype(np.float64) for f in factors]
+                forms["bf16"]["rel_err_vs_fp64_on_bf16_factors_sampled"] = sampled_rel_errors(
+                    st, rounded, host_outs, R, np.random.default_rng(8))
+                del rounded
+                log("bf16 sampled rel errors %s / on bf16 factors %s" % (
+                    forms["bf16"]["rel_err_vs_fp64_sampled"], forms["bf16"]["rel_err_vs_fp64_on_bf16_factors_sampled"]))
+            del host_outs
         val64 = st.val.astype(np.float64)
         crng = np.random.default_rng(11)
 
