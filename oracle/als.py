@@ -12,6 +12,10 @@ is taken here (the reading is listed with the others in the design notes):
     M   = X_(d) (Khatri-Rao product of the other factors)      (Eq. 1/2)
     V   = Hadamard product over w != d of  A_w^T A_w             (R x R)
     A_d = M V^{-1}                      (least-squares solution for mode d)
+          V_rr = prod_{w != d} ||A_w(:, r)||^2 is zero exactly when some other
+          factor's column r is zero; then row and column r of V are zero, the
+          system is solved on the other indices and A_d(:, r) = 0 (the
+          minimum-norm solution)
     lambda_r = ||A_d(:, r)||_2,  A_d(:, r) /= lambda_r   (0-norm columns stay 0)
 
 and after the last mode the fit of the CP model to the full tensor (missing
@@ -69,7 +73,13 @@ def cp_als_sweep(idx, val, dims, factors, trace=None):
         for w in range(N):
             if w != d:
                 V = V * G[w]
-        A = np.linalg.solve(V, M.T).T          # M V^{-1}; V is symmetric
+        live = np.diag(V) > 0
+        if live.all():
+            A = np.linalg.solve(V, M.T).T      # M V^{-1}; V is symmetric
+        else:
+            A = np.zeros_like(M)
+            if live.any():
+                A[:, live] = np.linalg.solve(V[np.ix_(live, live)], M[:, live].T).T
         lam = np.sqrt(np.sum(A * A, axis=0))
         nz = lam > 0
         A[:, nz] = A[:, nz] / lam[nz]

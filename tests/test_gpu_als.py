@@ -177,3 +177,29 @@ def test_orders_two_and_five(dims, rank):
     log("order %d: errs %s fit %.6f vs %.6f" % (len(dims), ["%.1e" % e for e in errs], fit, fo))
     assert max(errs) <= 1e-4 and abs(fit - fo) <= 1e-5
     assert oracle.rel_fro(lam, lo) <= 1e-4
+
+
+def test_zero_factor_column_stays_zero():
+    """A zero column in factor 1 makes V singular for the other modes (its
+    pivot is replaced by a tiny one on the GPU): column 2 of every factor ends
+    zero with lambda 0, and the rest follows the oracle's restricted solve."""
+    dims = (2000, 1500, 1000)
+    st = synth.tensor(dims, 40000, "zipf", 1.1, 0.0, seed=95)
+    rng = np.random.default_rng(95)
+    F0 = [rng.uniform(-1, 1, (d, 8)).astype(np.float32) for d in dims]
+    F0[1][:, 2] = 0.0
+    t = api.Tensor(st.idx, st.val, dims)
+    dF = [_dev(f) for f in F0]
+    lam, fit = api.cp_als_sweep(t, dF)
+    torch.cuda.synchronize()
+    Fo, lo, fo = als.cp_als_sweep(st.idx, st.val, dims, [f.astype(np.float64) for f in F0])
+    F = [f.cpu().numpy() for f in dF]
+    lam = lam.cpu().numpy()
+    log("zero column: lambda %s, fit %.6f vs %.6f" % (lam, float(fit.item()), fo))
+    for d in range(3):
+        assert not F[d][:, 2].any()
+        assert oracle.rel_fro(F[d], Fo[d]) <= 1e-4
+    assert lam[2] == 0.0 and lo[2] == 0.0
+    assert oracle.rel_fro(lam, lo) <= 1e-4
+    assert abs(float(fit.item()) - fo) <= 1e-5
+    t.close()

@@ -198,3 +198,24 @@ def test_mutants_fail_a_pin(name):
     if not np.allclose(np.linalg.norm(F[0], axis=0), 1.0):
         failed.append("normalisation")
     assert failed, "mutant %s passed every pin" % name
+
+
+def test_zero_factor_column_gives_the_smaller_rank_sweep():
+    """A zero column r in factor 1 zeroes row and column r of V for the other
+    modes: the update leaves column r zero in every mode with lambda_r = 0, and
+    the other columns, lambda and the fit are those of the rank R-1 sweep
+    without column r."""
+    dims = (8, 7, 6)
+    idx, val = _sparse(dims, 150, 11)
+    rng = np.random.default_rng(11)
+    F = [rng.standard_normal((d, 4)) for d in dims]
+    F[1][:, 2] = 0.0
+    G, lam, fit = als.cp_als_sweep(idx, val, dims, F)
+    keep = [0, 1, 3]
+    Gs, lams, fits = als.cp_als_sweep(idx, val, dims, [f[:, keep] for f in F])
+    for d in range(3):
+        assert not G[d][:, 2].any()
+        np.testing.assert_allclose(G[d][:, keep], Gs[d], rtol=1e-9, atol=1e-12)
+    assert lam[2] == 0.0
+    np.testing.assert_allclose(lam[keep], lams, rtol=1e-9)
+    assert abs(fit - fits) < 1e-10
