@@ -613,9 +613,14 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
                 if constexpr (OWN) {
                     // the own row is read where the key changes (and at a
                     // tile's first entry); elsewhere consume reuses the row
-                    // it holds, and the load, at -1, returns zeros
+                    // it holds.  Lanes that need none load at -1 (zeros), and
+                    // when no group of the wave needs one the load instruction
+                    // is skipped altogether (a wave-uniform branch, so the
+                    // address unit does no work for it)
                     const bool same = j0 + ju > 0 && kk[ju] == (ju == 0 ? kprev : kk[ju > 0 ? ju - 1 : 0]);
-                    own[ju] = gather_own((ix[0][ju] == -1 || same) ? -1 : kk[ju]);  // -1: padding
+                    const bool need = !(ix[0][ju] == -1 || same);   // -1: padding
+                    if (__builtin_amdgcn_ballot_w64(need) != 0) own[ju] = gather_own(need ? kk[ju] : -1);
+                    else own[ju] = typename OwnRow::Raw{};
                 }
             }
         };
