@@ -174,3 +174,12 @@ def test_host_layout_needs_only_two_shards_of_device_memory():
     assert _create_status(3, dims, nnz, ip, vp, (0, cap, 0, 1, 8192)) in (api.OK, api.ERR_UNSUPPORTED)
     # the default shard (2^25 nonzeros) is clipped to the tensor: one chunk-rounded shard
     assert _create_status(3, dims, nnz, ip, vp, (0, cap, 0, 1, 0)) == api.ERR_NOMEM
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout.strip()
