@@ -183,3 +183,24 @@ def test_streamed_orders_2_5_8(dims, rank):
     ref_loss, _ = oracle.cp_loss(idx, val, factors)
     assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
     t.close()
+
+
+def test_streamed_chained_als_sweeps_reuse_grams():
+    """Three chained sweeps on a streamed tensor, the later ones reusing the
+    Gram matrices the previous sweep left, each against the oracle's sweep
+    from the same factors."""
+    dims = (900, 700, 500)
+    st = _zipf(dims, 30000, seed=28, hot=0.0)
+    rng = np.random.default_rng(28)
+    F0 = [rng.uniform(-1, 1, (d, 12)).astype(np.float32) for d in dims]
+    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=128, host_layout=True, shard_nnz=2048)
+    dF = dev_factors(F0)
+    for s in range(3):
+        start = [f.cpu().numpy().astype(np.float64) for f in dF]
+        lam, fit = api.cp_als_sweep(t, dF, reuse_grams=s > 0)
+        Fo, lo, fo = als.cp_als_sweep(st.idx, st.val, dims, start)
+        errs = [oracle.rel_fro(dF[d].cpu().numpy(), Fo[d]) for d in range(3)]
+        log("streamed chained sweep %d: errs %s fit %.6f vs %.6f" % (s, ["%.1e" % e for e in errs],
+                                                                     float(fit.item()), fo))
+        assert max(errs) <= 1e-4 and abs(float(fit.item()) - fo) <= 1e-5
+    t.close()
