@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     constexpr int kWaves = kMttkrpBlock / 64;
     constexpr int G = 64 / LPR;
     constexpr int RT = LPR * RPL;
-    // nonzeros per group per batch: the forms that also read the output
-    // mode's row, and high orders, keep fewer rows in flight per batch
+    // nonzeros per group per batch: the loss and high orders keep fewer rows
+    // in flight per batch
     constexpr int U = (KIND != 2 && NIN <= AMPED_UMAX_NIN) ? (KIND == 0 ? AMPED_UMAX : AMPED_UMAX_GRAD)
                                                           : AMPED_UMAX_OWN;
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
