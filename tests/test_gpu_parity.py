@@ -217,6 +217,32 @@ def test_non_default_stream_and_reuse_of_output():
     t.close()
 
 
+def test_modes_on_concurrent_streams():
+    """Different modes of one tensor have their own work queues, so their
+    calls may overlap on different streams (default priority); five rounds of
+    all three modes at once, each output against the oracle."""
+    st = synth.tensor((5000, 3000, 2000), 80000, "zipf", 1.1, 0.05, seed=12)
+    factors = synth.factors(st.dims, 32, seed=12)
+    t = _tensor(st.idx, st.val, st.dims, chunk_nnz=256)
+    dfac = dev_factors(factors)
+    refs = [oracle_mttkrp(st.idx, st.val, st.dims, factors, d) for d in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = [torch.empty((st.dims[d], 32), dtype=torch.float32, device="cuda") for d in range(3)]
+    torch.cuda.synchronize()
+    for _ in range(5):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        for d, s in enumerate(streams):
+            with torch.cuda.stream(s):
+                f = [None if w == d else x for w, x in enumerate(dfac)]
+                api.mttkrp(t, d, f, out=outs[d], stream=s)
+        torch.cuda.synchronize()
+        for d in range(3):
+            assert rel(outs[d].cpu().numpy(), refs[d]) <= TOL
+    t.close()
+
+
 def test_call_errors_on_device():
     from ctypes import c_void_p
     st = synth.tensor((300, 200, 100), 2000, "zipf", 1.1, 0.0, seed=9)
