@@ -42,8 +42,11 @@ def measured_traffic(workload, lib_path):
     return None, None
 
 
+T0 = time.time()
+
+
 def log(msg):
-    print("[bench] " + msg, file=sys.stderr, flush=True)
+    print("[bench +%.0fs] %s" % (time.time() - T0, msg), file=sys.stderr, flush=True)
 
 
 def parse():
@@ -51,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf3-10Mx5Mx2M-200M")
+    ap.add_argument("--workload", default="skew3-100Mx50Mx10M-1B")
     ap.add_argument("--nnz", type=int, default=None, help="override the workload's nonzero count")
     ap.add_argument("--rank", type=int, default=None, help="override the workload's rank")
     ap.add_argument("--chunk", type=int, default=0)
@@ -82,30 +85,138 @@ def slice_stats(st):
     return out
 
 
-def sampled_rel_errors(st, factors64, outs, rank, rng, n_rows=200):
+def host_info():
+    """Cores this process may run on, the CPU model name and the host RAM."""
+    cores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        import subprocess
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    ram_gb = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram_gb = int(line.split()[1]) * 1024 / 1e9
+                break
+    except OSError:
+        pass
+    return cores, model, ram_gb
+
+
+def oracle_rows(st, factors64, d, rows, R, pool, parts):
+    """FP64 oracle MTTKRP of mode d on the given output rows only.
+
+    The nonzeros of those rows are split into `parts` pieces by position and
+    each piece runs through the unchanged sequential oracle on its own thread;
+    the per-piece outputs are added in fp64 (MTTKRP is linear in the tensor
+    values, so this changes only the fp64 summation order).  Called from the
+    CPU-baseline leg only."""
+    import oracle
+    lut = np.full(st.dims[d], -1, dtype=np.int64)
+    lut[rows] = np.arange(rows.size)
+    m = np.flatnonzero(lut[st.idx[d]] >= 0)
+    dims = list(st.dims)
+    dims[d] = rows.size
+    fs = list(factors64)
+    fs[d] = np.zeros((rows.size, R))
+
+    def piece(sl):
+        sub = st.idx[:, m[sl]].copy()
+        sub[d] = lut[sub[d]]
+        return oracle.mttkrp(sub, st.val[m[sl]], dims, fs, d)
+    bounds = np.linspace(0, m.size, parts + 1).astype(np.int64)
+    outs = list(pool.map(piece, [slice(bounds[i], bounds[i + 1]) for i in range(parts)]))
+    return np.sum(outs, axis=0)
+
+
+def sampled_rel_errors(st, factors64, outs, rank, rng, pool, parts, n_rows=200):
     """Relative Frobenius error of each mode's output on sampled rows (the
     heaviest row plus random touched rows) against the FP64 oracle.  Called
     from the CPU-baseline leg only."""
     import oracle
     errs = []
     for d, out in enumerate(outs):
-        col = st.idx[d]
-        counts = np.bincount(col, minlength=st.dims[d])
+        counts = np.bincount(st.idx[d], minlength=st.dims[d])
         touched = np.flatnonzero(counts)
         pick = rng.choice(touched, size=min(n_rows, touched.size), replace=False)
         rows = np.unique(np.concatenate([pick, [int(np.argmax(counts))]]))
-        lut = np.full(st.dims[d], -1, dtype=np.int64)
-        lut[rows] = np.arange(rows.size)
-        m = lut[col] >= 0
-        sub = st.idx[:, m].copy()
-        sub[d] = lut[sub[d]]
-        dims = list(st.dims)
-        dims[d] = rows.size
-        fs = list(factors64)
-        fs[d] = np.zeros((rows.size, rank))
-        ref = oracle.mttkrp(sub, st.val[m], dims, fs, d)
+        ref = oracle_rows(st, factors64, d, rows, rank, pool, parts)
         errs.append(oracle.rel_fro(out[rows], ref))
     return errs
+
+
+def row_block_jobs(idx, val, dims, factors64, d, parts):
+    """Split mode d's MTTKRP into at most `parts` blocks of output rows,
+    balanced by nonzero count and cut at row boundaries (equal row ranges when
+    there are no nonzeros).  Returns the row bounds and, per block, the
+    arguments of one oracle call with the block's rows relabelled to start at
+    0; the blocks' outputs stacked in order are the full mode-d output."""
+    S = val.size
+    R = factors64[0].shape[1]
+    key = idx[d]
+    if S:
+        cum = np.cumsum(np.bincount(key, minlength=dims[d]))
+        cuts = np.searchsorted(cum, np.arange(1, parts) * (S / parts), side="left") + 1
+    else:
+        cuts = np.arange(1, parts) * (dims[d] // parts)
+    bounds = np.unique(np.concatenate([[0], np.minimum(cuts, dims[d]), [dims[d]]])).astype(np.int64)
+    blk = (np.searchsorted(bounds, key, side="right") - 1).astype(np.int16)
+    order = np.argsort(blk, kind="stable")
+    starts = np.searchsorted(blk[order], np.arange(bounds.size - 1), side="left")
+    ends = np.append(starts[1:], S)
+    jobs = []
+    for b in range(bounds.size - 1):
+        o = order[starts[b]:ends[b]]
+        sub = idx[:, o]
+        sub[d] -= int(bounds[b])
+        bdims = list(dims)
+        bdims[d] = int(bounds[b + 1] - bounds[b])
+        fs = list(factors64)
+        fs[d] = np.zeros((1, R))
+        jobs.append((np.ascontiguousarray(sub), val[o], bdims, fs, d))
+    return bounds, jobs
+
+
+def cpu_baseline(st, factors64, pool, cores, target_s):
+    """The FP64 oracle timed on every core of this process's affinity set.
+
+    A strided sample of the tensor's nonzeros (every k-th one, so it spans the
+    whole tensor) is split, per mode, into one block of output rows per core,
+    balanced by nonzero count and cut at row boundaries; each block runs
+    through the unchanged sequential oracle on its own thread with its rows
+    relabelled to start at 0, so the blocks' outputs together are the
+    full-size output, zeroed as in the sequential oracle.  The timed wall clock
+    covers those per-mode block runs; the sample size follows the model
+    t(S) = a + b S fitted on a zero-nonzero and a pilot run."""
+    import oracle
+    N = st.order
+
+    def sample(S):
+        stride = max(1, st.nnz // max(S, 1))
+        sel = np.arange(stride // 2, st.nnz, stride, dtype=np.int64)[:S] if S else np.zeros(0, np.int64)
+        return st.idx[:, sel], st.val[sel].astype(np.float64)
+
+    def run(S):
+        idx, val = sample(S)
+        t = 0.0
+        for d in range(N):
+            _, jobs = row_block_jobs(idx, val, st.dims, factors64, d, cores)
+            t0 = time.perf_counter()
+            list(pool.map(lambda j: oracle.mttkrp(*j).shape, jobs))
+            t += time.perf_counter() - t0
+            del jobs
+        return t
+
+    t_zero = run(0)
+    S0 = int(min(st.nnz, 2_000_000 * cores))
+    b_per = max(run(S0) - t_zero, 1e-9) / S0
+    S = int(min(st.nnz, max(S0, (target_s - t_zero) / b_per)))
+    return S, run(S), t_zero
 
 
 def main():
@@ -339,15 +450,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         # the CPU-baseline leg: the only place the bench runs the oracle.  It checks
-        # sampled output rows of the GPU runs, then times the oracle on a sample.
+        # sampled output rows of the GPU runs, then times the oracle on a sample,
+        # on every core of this process's affinity set.
+        import concurrent.futures
         import oracle
+        cores, cpu_model, ram_gb = host_info()
+        pool = concurrent.futures.ThreadPoolExecutor(cores)
         factors64 = [f.astype(np.float64) for f in factors]
         if not args.no_accuracy:
             step(dfac)
             torch.cuda.synchronize()
             host_outs = [o.cpu().numpy() for o in outs]
             acc["fp32_rel_err_sampled"] = sampled_rel_errors(st, factors64, host_outs, R,
-                                                             np.random.default_rng(7))
+                                                             np.random.default_rng(7), pool, cores)
             log("fp32 sampled rel errors %s" % acc["fp32_rel_err_sampled"])
             if "bf16" in forms:
                 step(dbf, bf16=True)
@@ -356,33 +471,24 @@ def main():
                 # against the oracle on the fp32 factors (the bf16 error), and on the
                 # bf16-rounded factors (shows the accumulation stayed fp32); same rows
                 forms["bf16"]["rel_err_vs_fp64_sampled"] = sampled_rel_errors(
-                    st, factors64, host_outs, R, np.random.default_rng(8))
+                    st, factors64, host_outs, R, np.random.default_rng(8), pool, cores)
                 rounded = [oracle.bf16_to_f32(oracle.bf16_rne(f)).astype(np.float64) for f in factors]
                 forms["bf16"]["rel_err_vs_fp64_on_bf16_factors_sampled"] = sampled_rel_errors(
-                    st, rounded, host_outs, R, np.random.default_rng(8))
+                    st, rounded, host_outs, R, np.random.default_rng(8), pool, cores)
                 del rounded
                 log("bf16 sampled rel errors %s / on bf16 factors %s" % (
-                    forms["bf16"]["rel_err_vs_fp64_sampled"], forms["bf16"]["rel_err_vs_fp64_on_bf16_factors_sampled"]))
+                    forms["bf16"]["rel_err_vs_fp64_sampled"],
+                    forms["bf16"]["rel_err_vs_fp64_on_bf16_factors_sampled"]))
             del host_outs
-        val64 = st.val.astype(np.float64)
-        crng = np.random.default_rng(11)
-
-        def run_sample(S):
-            sel = np.sort(crng.choice(st.nnz, size=S, replace=False)) if S else np.zeros(0, np.int64)
-            sub, sv = np.ascontiguousarray(st.idx[:, sel]), val64[sel]
-            c0 = time.perf_counter()
-            for d in range(N):
-                oracle.mttkrp(sub, sv, st.dims, factors64, d)
-            return time.perf_counter() - c0
-        # time model t(S) = a + b*S (a: zeroing the full-size outputs)
-        t_zero = run_sample(0)
-        S0 = min(st.nnz, 1_000_000)
-        b_per = max(run_sample(S0) - t_zero, 1e-9) / S0
-        S = int(min(st.nnz, max(S0, (args.cpu_seconds - t_zero) / b_per)))
-        t_cpu = run_sample(S)
-        cpu = {"value": N * S / t_cpu, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-               "sample": "%d random nonzeros of the same tensor, all %d modes, full-size factors and "
-                         "outputs (zeroing included), float64, one thread; %.1fs" % (S, N, t_cpu)}
+        S, t_cpu, t_zero = cpu_baseline(st, factors64, pool, cores, args.cpu_seconds)
+        pool.shutdown()
+        cpu_value = N * S / t_cpu
+        cpu = {"value": cpu_value, "unit": "nnz/s", "cores": cores, "kind": "oracle",
+               "sample": "every %d-th nonzero of the same tensor (%d nonzeros), all %d modes; per mode one "
+                         "block of output rows per core (balanced by nonzeros), each through the sequential "
+                         "float64 oracle on its own thread; full-size factors, outputs zeroed (%.1fs of the "
+                         "%.1fs); wall clock" % (max(1, st.nnz // max(S, 1)), S, N, t_zero, t_cpu),
+               "cpu_model": cpu_model, "host_ram_GB": ram_gb, "seconds": t_cpu}
         log("cpu baseline %s" % cpu)
 
     traffic, traffic_src = measured_traffic(wl.name, api.LIB_PATH)
@@ -391,6 +497,8 @@ def main():
     mean_launch_s = float(np.mean(per_mode_ms)) * 1e-3
     fabric_gbps = traffic / mean_launch_s / 1e9 if traffic is not None else None
     value = N * st.nnz / (ms_step * 1e-3)
+    if cpu is not None:
+        cpu["gpu_over_cpu"] = value / cpu["value"]
     res = {
         "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

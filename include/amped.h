@@ -107,23 +107,40 @@ amped_status amped_tensor_create(int order, const int64_t *dims, int64_t nnz,
                                  const int32_t *indices, const float *values,
                                  const amped_options *opts, amped_tensor_t *out);
 
-/* Synchronise the handle's device, free everything it owns.  NULL is a no-op. */
+/*
+ * Release a tensor: the N per-mode copies of the tensor that the paper keeps
+ * for the N output modes (Sec. 3, "Tensor Partitioning"; Table 1, copies of
+ * the tensor) and the handle's work queues and row lists.  Synchronises the
+ * handle's device first, then frees everything the handle owns; the caller's
+ * factors and outputs are untouched.  NULL is a no-op.  Errors: HIP if the
+ * synchronisation reports an earlier device fault (the handle is freed anyway).
+ */
 amped_status amped_tensor_destroy(amped_tensor_t t);
 
 /*
- * Shape and layout facts (all outputs host and nullable):
- *   order; dims[order]; nnz; chunk_nnz (CH); n_chunks = ceil(nnz / CH);
- *   touched[order] = number of distinct output indices per mode;
+ * Shape and layout facts of a tensor (all outputs host and nullable):
+ *   order; dims[order]; nnz;
+ *   chunk_nnz (CH) and n_chunks = ceil(nnz / CH): the size and number of the
+ *     equal-size partitions each mode's copy is cut into (Sec. 3.1/3.2,
+ *     inter-shard partitioning);
+ *   touched[order] = distinct output indices per mode, i.e. the rows of the
+ *     mode's MTTKRP output that some nonzero updates (Sec. 3.1: all nonzeros
+ *     of one output index sit in one partition run);
  *   device_bytes = device memory the handle owns.
+ * Errors: INVALID for a NULL tensor.
  */
 amped_status amped_tensor_info(amped_tensor_t t, int *order, int64_t *dims, int64_t *nnz,
                                int64_t *chunk_nnz, int64_t *n_chunks, int64_t *touched,
                                int64_t *device_bytes);
 
 /*
- * Copy mode `mode`'s layout (from the device, or from the pinned host copy
- * with host_layout) to host arrays (introspection and tests; synchronous).
- * All outputs are nullable:
+ * Copy mode `mode`'s layout -- the mode's copy of the tensor with all
+ * nonzeros of one output index together (Sec. 3.1, tensor sharding), in the
+ * key order described at amped_tensor_create, cut into equal-size partitions
+ * (Sec. 3.1/3.2) -- from the device, or from the pinned host copy with
+ * host_layout, to host arrays (introspection and tests; synchronous).
+ * Errors: INVALID for a NULL tensor, a bad mode, or perm requested without
+ * keep_perm; HIP if a copy fails.  All outputs are nullable:
  *   perm        int32 [nnz]   position -> input nonzero (needs keep_perm=1,
  *                             else INVALID when requested)
  *   out_idx     int32 [nnz]   i_mode in layout order (non-decreasing)
@@ -138,9 +155,15 @@ amped_status amped_tensor_layout(amped_tensor_t t, int mode, int32_t *perm, int3
 
 /*
  * The same per-mode order and chunk flags, computed on the host only (no
- * device involved; the builder amped_tensor_create uses with host_layout, and
- * the order its device builder produces).  perm: int32 [nnz];
- * chunk_flags: uint8 [ceil(nnz/chunk_nnz)]; either may be NULL.
+ * device involved): the host preprocessing that builds a mode's partitioned
+ * copy of the tensor (Sec. 3.1/3.2; its cost is the preprocessing time of
+ * Sec. 5.7).  It is the builder amped_tensor_create uses with host_layout,
+ * and its order is the one the device builder produces.
+ *   indices     host, int32 [order][nnz], need not be sorted
+ *   perm        host, int32 [nnz], position -> input nonzero (nullable)
+ *   chunk_flags host, uint8 [ceil(nnz/chunk_nnz)] (nullable)
+ * Errors: INVALID for bad arguments or chunk_nnz < 1, RANGE for an index
+ * outside its mode, NOMEM.
  */
 amped_status amped_layout_host(int order, const int64_t *dims, int64_t nnz,
                                const int32_t *indices, int mode, int64_t chunk_nnz,
@@ -243,10 +266,15 @@ amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void 
 amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float *const *factors, double *lambda,
                                 double *fit, unsigned flags, void *stream);
 
-/* Message for the last non-OK status on this thread ("" if none). */
+/*
+ * Message for the last non-OK status on this thread ("" if none).  Not an
+ * operation of the paper: the error channel of every call above (the paper's
+ * Alg. 1-3 define no failure behaviour).  The string is owned by the library
+ * and valid until the next call on the same thread.
+ */
 const char *amped_last_error(void);
 
-/* Library version string. */
+/* Library version string (static storage).  Not an operation of the paper. */
 const char *amped_version(void);
 
 #ifdef __cplusplus

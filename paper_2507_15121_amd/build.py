@@ -3,6 +3,8 @@
 * ``libamped.so``       -- the C-ABI library: host layout builder (g++/OpenMP)
                            and the gfx950 HIP kernels (hipcc).
 * ``libamped_synth.so`` -- the seeded input generator (gcc/OpenMP), host only.
+* ``libamped_qstats.so`` -- libamped.so built with AMPED_QUEUE_STATS=1: the
+                           load-balance diagnostic (per-wave work-queue records).
 
 Every call recompiles.  ``python -m paper_2507_15121_amd.build`` runs it.
 """
@@ -22,6 +24,8 @@ ARCH = "gfx950"
 
 LIB = os.path.join(HERE, "libamped.so")
 SYNTH_LIB = os.path.join(HERE, "libamped_synth.so")
+# load-balance diagnostic build: per-wave work-queue records (include/amped_diag.h)
+QSTATS_LIB = os.path.join(HERE, "libamped_qstats.so")
 
 HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_loss.hip", "sort.hip",
                "als.hip"]
@@ -53,8 +57,8 @@ def build_synth(verbose=False):
     return SYNTH_LIB
 
 
-def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None):
-    """Build libamped.so (or, with `out`, a variant with extra hipcc flags)."""
+def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None, extra_host_flags=()):
+    """Build libamped.so (or, with `out`, a variant with extra compiler flags)."""
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     lib_path = out or LIB
     bdir = build_dir or BUILD_DIR
@@ -66,7 +70,7 @@ def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None):
                      ["-I" + INCLUDE, "-I" + CSRC, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HOST_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        jobs.append((["g++"] + HOST_FLAGS + ["-I" + INCLUDE, "-I" + CSRC, "-c",
+        jobs.append((["g++"] + HOST_FLAGS + list(extra_host_flags) + ["-I" + INCLUDE, "-I" + CSRC, "-c",
                                             os.path.join(CSRC, src), "-o", obj], obj))
     workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
@@ -80,9 +84,17 @@ def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None):
     return lib_path
 
 
+def build_qstats(verbose=False):
+    """The load-balance diagnostic variant of libamped.so."""
+    flag = ["-DAMPED_QUEUE_STATS=1"]
+    return build_amped(verbose, extra_hip_flags=flag, extra_host_flags=flag, out=QSTATS_LIB,
+                       build_dir=os.path.join(BUILD_DIR, "qstats"))
+
+
 def build(verbose=False):
     build_synth(verbose)
     build_amped(verbose)
+    build_qstats(verbose)
 
 
 if __name__ == "__main__":

@@ -13,6 +13,9 @@
 #include <vector>
 
 #include "amped.h"
+#if AMPED_QUEUE_STATS
+#include "amped_diag.h"
+#endif
 #include "internal.h"
 
 using amped::HostModeLayout;
@@ -233,7 +236,7 @@ amped_status upload_tables(amped_tensor_s* t, ModeDev& m, int d, const HostModeL
     m.zero_row = aux;
     m.sink = static_cast<float*>(aux) + 4;
     m.n_gaps = (int64_t)lay.gaps.size() / 2;
-    m.queue = static_cast<int*>(queues) + d;
+    m.queue = static_cast<unsigned*>(queues) + (size_t)d * amped::kQueueSlots;
     t->flags[d] = lay.flags;
     t->touched[d] = lay.touched;
 cleanup:
@@ -251,8 +254,8 @@ amped_status build_host_layout(amped_tensor_s* t, const int32_t* indices, const 
     void* queues = nullptr;
     void* aux = nullptr;
     void* p = nullptr;
-    HIP_OR_FAIL(t->alloc(&queues, (size_t)(order + 1) * sizeof(int)), "hipMalloc(queues)");
-    HIP_OR_FAIL(hipMemset(queues, 0, (size_t)(order + 1) * sizeof(int)), "hipMemset(queues)");
+    HIP_OR_FAIL(t->alloc(&queues, (size_t)(order + 1) * amped::kQueueSlots * sizeof(unsigned)), "hipMalloc(queues)");
+    HIP_OR_FAIL(hipMemset(queues, 0, (size_t)(order + 1) * amped::kQueueSlots * sizeof(unsigned)), "hipMemset(queues)");
     HIP_OR_FAIL(t->alloc(&aux, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMalloc(aux)");
     HIP_OR_FAIL(hipMemset(aux, 0, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMemset(aux)");
     for (int b = 0; b < 2; ++b) {
@@ -297,7 +300,7 @@ amped_status build_host_layout(amped_tensor_s* t, const int32_t* indices, const 
         return fail(AMPED_ERR_NOMEM, "host allocation failed");
     }
     t->loss_dev = t->mode[0];
-    t->loss_dev.queue = static_cast<int*>(queues) + order;
+    t->loss_dev.queue = static_cast<unsigned*>(queues) + (size_t)order * amped::kQueueSlots;
 cleanup:
     return st;
 }
@@ -504,8 +507,10 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
         HIP_OR_FAIL(t->alloc(&d_vals, (size_t)nnz * 4), "hipMalloc(values)");
         if (nnz) HIP_OR_FAIL(hipMemcpy(d_vals, values, (size_t)nnz * 4, hipMemcpyHostToDevice), "hipMemcpy(values)");
         if (!keep_perm) HIP_OR_FAIL(t->alloc(&d_tmp_perm, (size_t)nnz * 4), "hipMalloc(perm)");
-        HIP_OR_FAIL(t->alloc(&d_queues, (size_t)(order + 1) * sizeof(int)), "hipMalloc(queues)");
-        HIP_OR_FAIL(hipMemset(d_queues, 0, (size_t)(order + 1) * sizeof(int)), "hipMemset(queues)");
+        HIP_OR_FAIL(t->alloc(&d_queues, (size_t)(order + 1) * amped::kQueueSlots * sizeof(unsigned)),
+                    "hipMalloc(queues)");
+        HIP_OR_FAIL(hipMemset(d_queues, 0, (size_t)(order + 1) * amped::kQueueSlots * sizeof(unsigned)),
+                    "hipMemset(queues)");
         // 16 zero bytes followed by the store sink
         HIP_OR_FAIL(t->alloc(&d_aux, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMalloc(aux)");
         HIP_OR_FAIL(hipMemset(d_aux, 0, (size_t)(4 + kSinkFloats) * sizeof(float)), "hipMemset(aux)");
@@ -574,7 +579,7 @@ amped_status amped_tensor_create(int order, const int64_t* dims, int64_t nnz, co
             if (st != AMPED_OK) goto cleanup;
         }
         t->loss_dev = t->mode[0];
-        t->loss_dev.queue = static_cast<int*>(d_queues) + order;
+        t->loss_dev.queue = static_cast<unsigned*>(d_queues) + (size_t)order * amped::kQueueSlots;
     } catch (const std::bad_alloc&) {
         st = fail(AMPED_ERR_NOMEM, "host allocation failed");
         goto cleanup;
@@ -874,6 +879,25 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
     w.have_grams = true;   // G now holds the Gram matrices of the factors just written
     return AMPED_OK;
 }
+
+#if AMPED_QUEUE_STATS
+amped_status amped_queue_stats(uint64_t* records, int64_t max_records, int64_t* n_records, int32_t* waves_per_block,
+                               double* clock_hz)
+{
+    g_err.clear();
+    if (!n_records || !waves_per_block || !clock_hz) return fail(AMPED_ERR_INVALID, "NULL output");
+    if (records && max_records < 0) return fail(AMPED_ERR_INVALID, "max_records < 0");
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e, "wall clock rate");
+    *clock_hz = 1e3 * khz;
+    int wpb = 0;
+    e = amped::queue_stats_copy(reinterpret_cast<unsigned long long*>(records), max_records, n_records, &wpb);
+    *waves_per_block = wpb;
+    return e == hipSuccess ? AMPED_OK : hip_fail(e, "amped_queue_stats");
+}
+#endif
 
 amped_status amped_cp_loss(amped_tensor_t t, int rank, const float* const* factors, double* loss, void* stream)
 {

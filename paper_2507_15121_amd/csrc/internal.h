@@ -27,6 +27,9 @@ constexpr int kSinkFloats = 512;
 // The init kernel zeroes untouched output rows: runs at least this long as
 // (start, length) ranges, shorter runs row by row from the zero-row list.
 constexpr int kLongGap = 16;
+// Work-queue counters per layout: the chunks are split into at most this many
+// contiguous stripes, each with its own counter (one stripe per XCD).
+constexpr int kQueueSlots = 8;
 
 // ----------------------------------------------------------------- host layout
 struct HostModeLayout {
@@ -80,7 +83,7 @@ struct ModeDev {
     const int32_t* zero_rows = nullptr;            // [n_zero]
     const int32_t* gaps = nullptr;                 // [2 * n_gaps]
     int64_t nnz = 0, chunk = 0, n_chunks = 0, rows = 0, n_zero = 0, n_gaps = 0;
-    int* queue = nullptr;                          // device work-queue counter
+    unsigned* queue = nullptr;                     // kQueueSlots device work-queue counters
     const int32_t* hot = nullptr;                  // hot-row tables of this mode [kHotTableLen]
     const void* zero_row = nullptr;                // 16 zero bytes
     float* sink = nullptr;                         // kSinkFloats floats of write-only scratch
@@ -129,6 +132,13 @@ struct LossArgs {
     hipStream_t stream = nullptr;
 };
 hipError_t launch_cp_loss(const LossArgs& a);
+
+#if AMPED_QUEUE_STATS
+// Diagnostic build: copy the per-wave work-queue records of the last
+// MTTKRP-shaped launch (4 words each: chunks, nonzeros, first-pop time, exit
+// time) after synchronising the device.
+hipError_t queue_stats_copy(unsigned long long* host, int64_t max_records, int64_t* n_records, int* waves_per_block);
+#endif
 
 // CP-ALS building blocks (csrc/als.hip).  G = A^T A (fp64) of a rows x R fp32
 // matrix, R <= 128, via gram_slabs(rows) x R x R fp32 partials.

@@ -4,47 +4,6 @@
 namespace amped {
 namespace dev {
 
-template <int NIN, typename T, int KIND, bool BUF>
-KernelFn pick_vec(int lpr)
-{
-    constexpr int RPL = 16 / sizeof(T);
-    if constexpr (NIN > kMaxVecNin) {
-        return nullptr;
-    } else {
-        switch (lpr) {
-        case 4: return mttkrp_kernel<NIN, 4, RPL, T, KIND, BUF>;
-        case 8: return mttkrp_kernel<NIN, 8, RPL, T, KIND, BUF>;
-        case 16: return mttkrp_kernel<NIN, 16, RPL, T, KIND, BUF>;
-        case 32:
-            if constexpr (std::is_same<T, float>::value) return mttkrp_kernel<NIN, 32, RPL, T, KIND, BUF>;
-            else return nullptr;
-        default: return nullptr;
-        }
-    }
-}
-
-template <int NIN, typename T, int KIND>
-KernelFn pick_nin(int lpr, bool scalar, bool buf)
-{
-    if (scalar) return mttkrp_kernel<NIN, 64, 1, T, KIND, false>;
-    return buf ? pick_vec<NIN, T, KIND, true>(lpr) : pick_vec<NIN, T, KIND, false>(lpr);
-}
-
-template <typename T, int KIND>
-KernelFn pick_any(int nin, int lpr, bool scalar, bool buf)
-{
-    switch (nin) {
-    case 1: return pick_nin<1, T, KIND>(lpr, scalar, buf);
-    case 2: return pick_nin<2, T, KIND>(lpr, scalar, buf);
-    case 3: return pick_nin<3, T, KIND>(lpr, scalar, buf);
-    case 4: return pick_nin<4, T, KIND>(lpr, scalar, buf);
-    case 5: return pick_nin<5, T, KIND>(lpr, scalar, buf);
-    case 6: return pick_nin<6, T, KIND>(lpr, scalar, buf);
-    case 7: return pick_nin<7, T, KIND>(lpr, scalar, buf);
-    default: return nullptr;
-    }
-}
-
 KernelFn pick_mttkrp_f32(int nin, int lpr, bool scalar, bool buf) { return pick_any<float, 0>(nin, lpr, scalar, buf); }
 
 }  // namespace dev

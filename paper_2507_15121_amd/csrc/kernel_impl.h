@@ -60,6 +60,12 @@ __host__ __device__ constexpr bool hot_cache_kind(int kind) { return kind == 0 |
 #ifndef AMPED_GATHER_AUX
 #define AMPED_GATHER_AUX 0
 #endif
+// Diagnostic build: every wave of the MTTKRP-shaped kernels records how many
+// chunks and nonzeros it took from the work queue and when it took its first
+// chunk and exited (constant-rate wall clock), for the load-balance report.
+#ifndef AMPED_QUEUE_STATS
+#define AMPED_QUEUE_STATS 0
+#endif
 constexpr int kMaxIn = kMaxOrder - 1;
 
 // Tuning knobs (compile-time): nonzeros per group whose gathers are issued
@@ -104,7 +110,8 @@ struct KParams {
     const float* own;
     float* out;
     double* loss;
-    int* queue;
+    unsigned* queue;  // n_stripes counters
+    int n_stripes;    // contiguous chunk stripes, one counter each (1..kQueueSlots)
     int64_t nnz, chunk, n_chunks, rows;
     int64_t ld;     // row stride of factors and output, in elements
     int col0;       // first column handled by this launch
@@ -118,6 +125,9 @@ struct KParams {
     int next_key;             // output index just after position nnz - 1 (-1: none)
     const int32_t* hot[kMaxIn];  // per input: direct-mapped table of hot_k rows kept in LDS
     int hot_k;                // LDS row-cache slots per input (power of two; 0 = none)
+#if AMPED_QUEUE_STATS
+    unsigned long long* qstats;  // per wave: chunks, nonzeros, first-pop and exit times
+#endif
 };
 
 // Dynamic LDS of the MTTKRP kernel: 16 zero bytes, then (vector path, K > 0)
@@ -317,12 +327,45 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int pop_chunk(int* queue, int lane)
-{
-    int c = 0;
-    if (lane == 0) c = atomicAdd(queue, 1);
-    return __builtin_amdgcn_readfirstlane(c);
-}
+// Work queue.  The chunks are split into S contiguous stripes, each with its
+// own counter.  A wave starts on stripe `home` and moves on to the next stripe
+// when one runs dry, so with one stripe per XCD the consecutive chunks of a
+// stripe (neighbouring output rows; for a heavy row, neighbouring input
+// indices) are taken by one XCD's CUs while any chunk is left on its stripe,
+// and no CU idles while any chunk is left anywhere.  With S = 1 this is one
+// global counter.  A wave reads each counter at most once past the end of its
+// stripe, so a counter never exceeds the stripe's chunks plus the waves of the
+// grid (below 2^32: chunks < 2^31), and it is compared as unsigned.
+struct ChunkQueue {
+    unsigned* q;
+    int64_t n_chunks;
+    int S, home, tried = 0;
+    int64_t b0 = 0, b1 = 0;   // current stripe's chunk range
+
+    __device__ __forceinline__ ChunkQueue(unsigned* q_, int64_t n, int stripes, int home_)
+        : q(q_), n_chunks(n), S(stripes), home(home_)
+    {
+        set_stripe();
+    }
+    __device__ __forceinline__ void set_stripe()
+    {
+        const int x = (home + tried) % S;
+        b0 = (int64_t)x * n_chunks / S;
+        b1 = (int64_t)(x + 1) * n_chunks / S;
+    }
+    // next chunk, or -1 when every stripe is exhausted (wave-uniform)
+    __device__ __forceinline__ int64_t pop(int lane)
+    {
+        while (tried < S) {
+            unsigned c = 0;
+            if (lane == 0) c = atomicAdd(q + (home + tried) % S, 1u);
+            c = (unsigned)__builtin_amdgcn_readfirstlane((int)c);
+            if ((int64_t)c < b1 - b0) return b0 + (int64_t)c;
+            if (++tried < S) set_stripe();
+        }
+        return -1;
+    }
+};
 
 // --------------------------------------------------------------- MTTKRP kernel
 // KIND 0: MTTKRP.  KIND 1: scale * MTTKRP of the residuals val - CP model,
@@ -455,11 +498,20 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     };
     const bool vec_meta = (p.chunk & 3) == 0;
 
+#if AMPED_QUEUE_STATS
+    unsigned long long st_chunks = 0, st_nnz = 0, st_first = 0;
+#endif
+    ChunkQueue cq(p.queue, p.n_chunks, p.n_stripes, (int)(blockIdx.x % (unsigned)p.n_stripes));
     for (;;) {
-        const int chunk = pop_chunk(p.queue, lane);
-        if (chunk >= p.n_chunks) break;
-        const int64_t cs = (int64_t)chunk * p.chunk;
+        const int64_t chunk = cq.pop(lane);
+        if (chunk < 0) break;
+        const int64_t cs = chunk * p.chunk;
         const int clen = (int)(min(cs + p.chunk, p.nnz) - cs);
+#if AMPED_QUEUE_STATS
+        if (st_chunks == 0) st_first = (unsigned long long)wall_clock64();
+        ++st_chunks;
+        st_nnz += (unsigned long long)clen;
+#endif
         const int Lg = ((clen + FS - 1) / FS) * TS;            // run length per group, whole tiles
         const int goff = g * Lg;                                // group's first position in the chunk
         const int len = max(0, min(Lg, clen - goff));           // nonzeros in the group's run
@@ -803,6 +855,15 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         }
         wave_lds_sync();
     }
+#if AMPED_QUEUE_STATS
+    if (lane == 0 && p.qstats) {
+        unsigned long long* r = p.qstats + ((size_t)blockIdx.x * kWaves + wv) * 4;
+        r[0] = st_chunks;
+        r[1] = st_nnz;
+        r[2] = st_first;
+        r[3] = (unsigned long long)wall_clock64();
+    }
+#endif
     if constexpr (KIND == 2) {
         // wave sum in fp64, one atomic per wave.  The first log2(LPR) steps add
         // equal values (every lane of a group holds the group's sum), so they
@@ -825,6 +886,64 @@ KernelFn pick_mttkrp_f32(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_mttkrp_bf16(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_grad(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_loss(int nin, int lpr, bool scalar, bool buf);
+
+// The instance each picker returns: lpr counts 16-byte lanes per row (the
+// vector path), scalar selects the column-tile path.  bfloat16 rows of up to
+// 64 bytes (rank <= 32) use 8 bytes per lane, so a wave still covers 8 rows
+// per gather at rank 32 (16-byte lanes would make 16 narrow groups).
+#ifndef AMPED_BF16_NARROW
+#define AMPED_BF16_NARROW 1
+#endif
+template <int NIN, typename T, int KIND, bool BUF>
+KernelFn pick_vec(int lpr)
+{
+    constexpr int RPL = 16 / sizeof(T);
+    constexpr bool narrow = AMPED_BF16_NARROW && std::is_same<T, uint16_t>::value;
+    if constexpr (NIN > kMaxVecNin) {
+        return nullptr;
+    } else {
+        if constexpr (narrow) {
+            if (lpr <= 4) {
+                switch (lpr) {
+                case 2: return mttkrp_kernel<NIN, 4, 4, T, KIND, BUF>;
+                case 4: return mttkrp_kernel<NIN, 8, 4, T, KIND, BUF>;
+                default: return nullptr;
+                }
+            }
+        }
+        switch (lpr) {
+        case 4: return mttkrp_kernel<NIN, 4, RPL, T, KIND, BUF>;
+        case 8: return mttkrp_kernel<NIN, 8, RPL, T, KIND, BUF>;
+        case 16: return mttkrp_kernel<NIN, 16, RPL, T, KIND, BUF>;
+        case 32:
+            if constexpr (std::is_same<T, float>::value) return mttkrp_kernel<NIN, 32, RPL, T, KIND, BUF>;
+            else return nullptr;
+        default: return nullptr;
+        }
+    }
+}
+
+template <int NIN, typename T, int KIND>
+KernelFn pick_nin(int lpr, bool scalar, bool buf)
+{
+    if (scalar) return mttkrp_kernel<NIN, 64, 1, T, KIND, false>;
+    return buf ? pick_vec<NIN, T, KIND, true>(lpr) : pick_vec<NIN, T, KIND, false>(lpr);
+}
+
+template <typename T, int KIND>
+KernelFn pick_any(int nin, int lpr, bool scalar, bool buf)
+{
+    switch (nin) {
+    case 1: return pick_nin<1, T, KIND>(lpr, scalar, buf);
+    case 2: return pick_nin<2, T, KIND>(lpr, scalar, buf);
+    case 3: return pick_nin<3, T, KIND>(lpr, scalar, buf);
+    case 4: return pick_nin<4, T, KIND>(lpr, scalar, buf);
+    case 5: return pick_nin<5, T, KIND>(lpr, scalar, buf);
+    case 6: return pick_nin<6, T, KIND>(lpr, scalar, buf);
+    case 7: return pick_nin<7, T, KIND>(lpr, scalar, buf);
+    default: return nullptr;
+    }
+}
 
 }  // namespace dev
 }  // namespace amped

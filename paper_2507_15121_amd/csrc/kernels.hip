@@ -48,12 +48,12 @@ namespace dev {
 // untouched rows.  vec4: ld, col0 and ncols are multiples of 4 (16-byte stores).
 __global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, int col0, int ncols, bool vec4,
                                                       const int32_t* zrows, int64_t n_zero,
-                                                      const int32_t* gaps, int64_t n_gaps, int* queue,
+                                                      const int32_t* gaps, int64_t n_gaps, unsigned* queue,
                                                       double* loss)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (queue) *queue = 0;
-        if (loss) *loss = 0.0;
+    if (blockIdx.x == 0) {
+        if (queue && threadIdx.x < kQueueSlots) queue[threadIdx.x] = 0u;
+        if (loss && threadIdx.x == 0) *loss = 0.0;
     }
     if (!out) return;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
@@ -101,6 +101,49 @@ struct Shape {
     size_t dyn = 16;
     int grid = 0;
 };
+
+// Work-queue stripes per launch (1..kQueueSlots): AMPED_QUEUE_STRIPES, read
+// once per process, else the default.
+#ifndef AMPED_DEFAULT_STRIPES
+#define AMPED_DEFAULT_STRIPES 1
+#endif
+int queue_stripes()
+{
+    static const int n = [] {
+        const char* e = std::getenv("AMPED_QUEUE_STRIPES");
+        const int v = (e && *e) ? std::atoi(e) : AMPED_DEFAULT_STRIPES;
+        return std::max(1, std::min(v, kQueueSlots));
+    }();
+    return n;
+}
+
+#if AMPED_QUEUE_STATS
+// Diagnostic build: the per-wave records of the last MTTKRP-shaped launch.
+struct QueueStats {
+    unsigned long long* dev = nullptr;
+    int64_t cap = 0, n = 0;
+    int waves_per_block = 0;
+} g_qstats;
+std::mutex g_qstats_mu;
+
+hipError_t qstats_attach(KParams& k, int grid, int block, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_qstats_mu);
+    const int64_t n = (int64_t)grid * (block / 64);
+    if (n > g_qstats.cap) {
+        if (g_qstats.dev) (void)hipFree(g_qstats.dev);
+        g_qstats.dev = nullptr;
+        g_qstats.cap = 0;
+        hipError_t e = hipMalloc(&g_qstats.dev, (size_t)n * 4 * sizeof(unsigned long long));
+        if (e != hipSuccess) return e;
+        g_qstats.cap = n;
+    }
+    g_qstats.n = n;
+    g_qstats.waves_per_block = block / 64;
+    k.qstats = g_qstats.dev;
+    return hipMemsetAsync(g_qstats.dev, 0, (size_t)n * 4 * sizeof(unsigned long long), st);
+}
+#endif
 
 int hot_cap()
 {
@@ -177,6 +220,7 @@ KParams base_params(const ModeDev& m)
     for (int w = 0; w < kMaxIn; ++w) k.in_idx[w] = m.in_idx[w];
     k.val = m.val;
     k.queue = m.queue;
+    k.n_stripes = queue_stripes();
     k.nnz = m.nnz;
     k.chunk = m.chunk;
     k.n_chunks = m.n_chunks;
@@ -255,12 +299,29 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
         if (m.n_chunks == 0) continue;
         k.col0 = col0;
         k.ncols = ncols;
+#if AMPED_QUEUE_STATS
+        if ((e = qstats_attach(k, sh.grid, block, a.stream)) != hipSuccess) return e;
+#endif
         void* args[] = {&k};
         e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(sh.grid), dim3(block), args, sh.dyn, a.stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
+
+#if AMPED_QUEUE_STATS
+hipError_t queue_stats_copy(unsigned long long* host, int64_t max_records, int64_t* n_records, int* waves_per_block)
+{
+    std::lock_guard<std::mutex> lk(g_qstats_mu);
+    *n_records = g_qstats.n;
+    *waves_per_block = g_qstats.waves_per_block;
+    if (!host || g_qstats.n == 0) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    const int64_t n = std::min(max_records, g_qstats.n);
+    return hipMemcpy(host, g_qstats.dev, (size_t)n * 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+}
+#endif
 
 hipError_t launch_cp_loss(const LossArgs& a)
 {
@@ -292,6 +353,9 @@ hipError_t launch_cp_loss(const LossArgs& a)
     const Shape sh = launch_shape(fn, block, a.order - 1, a.rank * 4, !scalar && hot_cache_kind(2));
     if (sh.grid <= 0) return hipErrorInvalidDevice;
     set_hot(k, sh.hot_k, a.in_hot, a.order - 1);
+#if AMPED_QUEUE_STATS
+    if ((e = qstats_attach(k, sh.grid, block, a.stream)) != hipSuccess) return e;
+#endif
     void* args[] = {&k};
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(sh.grid), dim3(block), args, sh.dyn, a.stream);
 }

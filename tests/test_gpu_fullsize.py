@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import log
+from gpu_util import log, oracle_rows, sample_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,42 @@ def test_fullsize_bf16_sampled_rows(big):
         e = oracle.rel_fro(got, _oracle_rows(st, f64, d, rows, R))
         log("bf16 mode %d: sampled rel %.2e vs fp64 oracle on fp32 factors" % (d, e))
         assert e <= 1e-2
+
+
+def test_fullsize_r64_fp32_and_bf16(big):
+    """The same 200M-nonzero tensor at R = 64 (256-byte fp32 rows, 16 lanes per
+    row; 128-byte bf16 rows): fp32 against the FP64 oracle at 1e-5; bf16
+    against the oracle on the bf16-rounded factors at 1e-5 (fp32 accumulation)
+    and against the oracle on the fp32 factors at 1e-2, per mode."""
+    st, _, T, _ = big
+    R = 64
+    factors = synth.factors(st.dims, R)
+    dfac = [torch.from_numpy(f).cuda() for f in factors]
+    dbf = [f.to(torch.bfloat16) for f in dfac]
+    rng = np.random.default_rng(64)
+
+    def bf16_round(f):
+        return oracle.bf16_to_f32(oracle.bf16_rne(f))
+    for d in range(3):
+        rows, counts, _ = sample_rows(st.idx[d], st.dims[d], rng, 200)
+        sel = torch.from_numpy(rows).cuda()
+        out = torch.full((st.dims[d], R), float("nan"), device="cuda")
+        api.mttkrp(T, d, [None if w == d else f for w, f in enumerate(dfac)], out=out)
+        torch.cuda.synchronize()
+        assert not torch.isnan(out).any().item()
+        got = out[sel].cpu().numpy()
+        out.fill_(float("nan"))
+        api.mttkrp_bf16(T, d, [None if w == d else f for w, f in enumerate(dbf)], out=out)
+        torch.cuda.synchronize()
+        assert not torch.isnan(out).any().item()
+        got_b = out[sel].cpu().numpy()
+        del out
+        ref, _ = oracle_rows(st.idx, st.val, st.dims, factors, d, rows)
+        ref_b, _ = oracle_rows(st.idx, st.val, st.dims, factors, d, rows, transform=bf16_round)
+        e, eb, ebf = oracle.rel_fro(got, ref), oracle.rel_fro(got_b, ref_b), oracle.rel_fro(got_b, ref)
+        log("R=64 mode %d: fp32 rel %.2e; bf16 rel %.2e vs oracle on bf16-rounded factors, %.2e vs fp32 factors" %
+            (d, e, eb, ebf))
+        assert e <= 1e-5 and eb <= 1e-5 and ebf <= 1e-2
 
 
 def test_factor_above_4GiB_uses_64bit_gathers():

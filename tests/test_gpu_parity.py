@@ -204,6 +204,43 @@ def test_device_layout_wide_keys_matches_host_builder(shuffle):
     t.close()
 
 
+def test_device_layout_bit_exact_above_256_scan_tiles():
+    """24M nonzeros: each radix pass scans 256 x 24M / 4096 digit counts in
+    tiles of 4096, i.e. 366 scan tiles, so the tile totals are scanned in two
+    carried rounds (more than 256 tiles appear from about 16.7M nonzeros on).
+    Shuffled input with 2M exact duplicates copied from other positions, a run
+    of 2M nonzeros with one mode-0 index and 300k identical coordinates: the
+    device layout of every mode (perm, out_idx, in_idx, values, chunk flags)
+    equals the host builder's, which the CPU tests pin to the oracle's
+    ordering, bit for bit."""
+    rng = np.random.default_rng(24)
+    dims = (5000, 300_000, 70_000)
+    nnz = 24_000_000
+    idx = np.stack([rng.integers(0, d, nnz, dtype=np.int32) for d in dims])
+    idx[0, :2_000_000] = 4321
+    idx[:, 2_000_000:2_300_000] = np.array([[17], [123_456], [65_432]], dtype=np.int32)
+    src = rng.integers(0, nnz, 2_000_000)
+    dst = rng.integers(0, nnz, 2_000_000)
+    idx[:, dst] = idx[:, src]
+    p = rng.permutation(nnz)
+    idx = np.ascontiguousarray(idx[:, p])
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    log("layout 24M: building on the device")
+    t = _tensor(idx, val, dims, keep_perm=True)
+    for d in range(3):
+        lay = t.layout(d, perm=True)
+        perm, flags = api.layout_host(idx, dims, d, 4096)
+        np.testing.assert_array_equal(lay["perm"], perm)
+        np.testing.assert_array_equal(lay["flags"], flags)
+        np.testing.assert_array_equal(lay["out_idx"], idx[d][perm])
+        others = [w for w in range(3) if w != d]
+        for j, w in enumerate(others):
+            np.testing.assert_array_equal(lay["in_idx"][j], idx[w][perm])
+        np.testing.assert_array_equal(lay["values"].view(np.uint32), val[perm].view(np.uint32))
+        log("layout 24M: mode %d equal to the host builder" % d)
+    t.close()
+
+
 def test_non_default_stream_and_reuse_of_output():
     st = synth.tensor((3000, 2000, 1000), 40000, "zipf", 1.1, 0.0, seed=8)
     factors = synth.factors(st.dims, 32, seed=8)
