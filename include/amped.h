@@ -234,6 +234,25 @@ amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float *co
 amped_status amped_gram(const float *A, int64_t rows, int rank, double *G, void *stream);
 
 /*
+ * amped_gram without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, and harnesses
+ * that forbid hipMalloc.  The result is amped_gram's (bit for bit up to rank
+ * 64; for larger ranks with many rows the rows are split into fewer slabs, so
+ * the fp64 sum of the fp32 slab partials may differ in the last bits).
+ *   A, rows, rank, G, stream  as in amped_gram
+ * The per-slab partial sums go to a fixed 32 MiB device array that the
+ * library keeps on every device it runs on until the process ends (no
+ * hipMalloc, hipFree or allocating call).  Every call on one device uses the
+ * same array and overwrites every entry it reads, so calls that overlap on
+ * one device (on different streams, or from different threads) race and must
+ * be ordered by the caller.  The first call on a device looks up the array's
+ * device address.  Errors: INVALID for a NULL pointer, rows < 1, or a rank
+ * outside [1, 128] (larger ranks' partial sums exceed the array); UNSUPPORTED
+ * for a device that is not gfx950; HIP for a failed launch.
+ */
+amped_status amped_gram_noalloc(const float *A, int64_t rows, int rank, double *G, void *stream);
+
+/*
  * One CP-ALS sweep (CPD by alternating least squares, Sec. 2.1; the mode
  * loop of Alg. 1 with the standard least-squares update after each MTTKRP):
  * for d = 0..N-1

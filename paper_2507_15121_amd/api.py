@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "RANGE", 3: "NOMEM", 4: "HIP", 5: "UNS
 # every symbol declared in include/amped.h
 EXPORTED = ["amped_tensor_create", "amped_tensor_destroy", "amped_tensor_info", "amped_tensor_layout",
             "amped_layout_host", "amped_mttkrp", "amped_mttkrp_bf16", "amped_cp_loss", "amped_cp_grad",
-            "amped_gram", "amped_cp_als_sweep", "amped_last_error", "amped_version"]
+            "amped_gram", "amped_gram_noalloc", "amped_cp_als_sweep", "amped_last_error", "amped_version"]
 
 
 class AmpedError(RuntimeError):
@@ -58,6 +58,7 @@ def lib():
         L.amped_cp_loss.argtypes = [vp, i32, pvp, vp, vp]
         L.amped_cp_grad.argtypes = [vp, i32, i32, pvp, ctypes.c_float, vp, vp]
         L.amped_gram.argtypes = [vp, i64, i32, vp, vp]
+        L.amped_gram_noalloc.argtypes = [vp, i64, i32, vp, vp]
         L.amped_cp_als_sweep.argtypes = [vp, i32, pvp, vp, vp, ctypes.c_uint, vp]
         for name in EXPORTED:
             if name not in ("amped_last_error", "amped_version"):
@@ -273,6 +274,21 @@ def gram(A, out=None, stream=None):
         raise ValueError("out must be a contiguous (rank, rank) float64 tensor")
     _check(lib().amped_gram(ctypes.c_void_p(A.data_ptr()), int(A.shape[0]), rank, ctypes.c_void_p(out.data_ptr()),
                             _stream_ptr(stream)))
+    return out
+
+
+def gram_noalloc(A, out, stream=None):
+    """A^T A like gram(), through the entry point that allocates nothing (its
+    partial sums use the library's fixed device array); `out` is required."""
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float32 or A.dim() != 2 \
+            or not A.is_contiguous():
+        raise ValueError("A must be a contiguous 2-D float32 CUDA/HIP tensor")
+    rank = int(A.shape[1])
+    if out.dtype != torch.float64 or tuple(out.shape) != (rank, rank) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (rank, rank) float64 tensor")
+    _check(lib().amped_gram_noalloc(ctypes.c_void_p(A.data_ptr()), int(A.shape[0]), rank,
+                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 
@@ -417,10 +418,11 @@ int64_t gram_slabs(int64_t rows)
     return std::max<int64_t>(1, std::min<int64_t>(n, 2048));
 }
 
-hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st)
+hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st,
+                       int64_t nslab)
 {
     if (R < 1 || R > 128) return hipErrorInvalidValue;
-    const int64_t nslab = gram_slabs(rows);
+    if (nslab <= 0) nslab = gram_slabs(rows);
     int64_t slab_rows = (rows + nslab - 1) / nslab;
     slab_rows += slab_rows & 1;
     const int T = (R + 31) / 32;
@@ -434,6 +436,54 @@ hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, doub
     }
     hipLaunchKernelGGL(gram_reduce, dim3((R * R + 31) / 32), dim3(256), 0, st, partial, nslab, R, G);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ Gram without allocation
+// The partial sums of amped_gram_noalloc live in this fixed device array
+// instead of memory allocated per call: kGramScratchFloats floats (32 MiB) on
+// every device the library runs on, held until the process ends.  Every call
+// on a device shares its array; gram_partial overwrites every entry the
+// reduction reads, so nothing has to be cleared between calls, and calls that
+// overlap on one device race on it.
+constexpr int64_t kGramScratchFloats = int64_t(8) << 20;
+static __device__ __align__(256) float scratch[kGramScratchFloats];
+
+namespace {
+// Device address of `scratch` per device, looked up once per device with that
+// device current (the host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+float* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+int64_t gram_noalloc_slabs(int64_t rows, int R)
+{
+    const int64_t fit = kGramScratchFloats / ((int64_t)R * R);
+    return std::min(gram_slabs(rows), fit);
+}
+
+hipError_t launch_gram_noalloc(const float* A, int64_t rows, int R, double* G, hipStream_t st)
+{
+    if (R < 1 || R > 128 || rows < 1) return hipErrorInvalidValue;
+    const int64_t nslab = gram_noalloc_slabs(rows, R);
+    if (nslab < 1 || nslab * (int64_t)R * R > kGramScratchFloats) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    float* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            g_scratch_ptr[dev] = static_cast<float*>(p);
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return launch_gram(A, rows, R, ptr, G, st, nslab);
 }
 
 hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, float* W,

@@ -781,6 +781,24 @@ amped_status amped_gram(const float* A, int64_t rows, int rank, double* G, void*
     return AMPED_OK;
 }
 
+amped_status amped_gram_noalloc(const float* A, int64_t rows, int rank, double* G, void* stream)
+{
+    g_err.clear();
+    if (!A || !G) return fail(AMPED_ERR_INVALID, "A or G is NULL");
+    if (rows < 1) return fail(AMPED_ERR_INVALID, "rows %lld < 1", (long long)rows);
+    if (rank < 1 || rank > 128)
+        return fail(AMPED_ERR_INVALID, "rank %d outside [1, 128]: the partial sums of larger ranks do not fit the "
+                    "fixed 32 MiB device scratch", rank);
+    int dev = 0;
+    amped_status st = check_device(&dev);
+    if (st != AMPED_OK) return st;
+    hipError_t e = amped::launch_gram_noalloc(A, rows, rank, G, static_cast<hipStream_t>(stream));
+    if (e == hipErrorInvalidValue)
+        return fail(AMPED_ERR_INVALID, "amped_gram_noalloc: %lld rows x rank %d exceed the fixed device scratch",
+                    (long long)rows, rank);
+    return e == hipSuccess ? AMPED_OK : hip_fail(e, "amped_gram_noalloc");
+}
+
 amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factors, double* lambda, double* fit,
                                 unsigned flags, void* stream)
 {

@@ -143,7 +143,13 @@ hipError_t queue_stats_copy(unsigned long long* host, int64_t max_records, int64
 // CP-ALS building blocks (csrc/als.hip).  G = A^T A (fp64) of a rows x R fp32
 // matrix, R <= 128, via gram_slabs(rows) x R x R fp32 partials.
 int64_t gram_slabs(int64_t rows);
-hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st);
+hipError_t launch_gram(const float* A, int64_t rows, int R, float* partial, double* G, hipStream_t st,
+                       int64_t nslab = 0);
+// The same with the partial sums in the library's fixed device array (no
+// allocation): at most gram_noalloc_slabs(rows, R) <= gram_slabs(rows) slabs,
+// so that they fit its 32 MiB.
+int64_t gram_noalloc_slabs(int64_t rows, int R);
+hipError_t launch_gram_noalloc(const float* A, int64_t rows, int R, double* G, hipStream_t st);
 // The R x R algebra of the mode-d update (scratch: 4 R x R doubles); G is
 // [N][R][R] and G[d] is replaced by the Gram matrix of the new factor.
 hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, float* W,
