@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) gram_reduce(const float* partial, int64_t
 // in 4 R x R doubles: LDS when they fit (dynamic, in_lds), else the global
 // scratch.  G: [N][R][R] (G[d] is replaced).
 __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int N, int d, int R, double* scratch,
-                                                 float* W, double* lambda, int last, const double* xnorm2,
+                                                 double* W, double* lambda, int last, const double* xnorm2,
                                                  double* fit, int in_lds)
 {
     extern __shared__ __align__(16) double s_small[];
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
         const int i = e / R, j = e % R;
         const double li = lambda[i], lj = lambda[j];
         G[(int64_t)d * RR + e] = (li > 0.0 && lj > 0.0) ? V[e] / (li * lj) : 0.0;
-        W[e] = lj > 0.0 ? (float)(Vi[e] / lj) : 0.f;
+        W[e] = lj > 0.0 ? Vi[e] / lj : 0.0;
     }
     __syncthreads();
     if (last) {
@@ -299,28 +299,32 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
     }
 }
 
-// A = M W for rows x R fp32 matrices (row-major), W R x R.  A block of 256
-// threads stages RB rows of M (row stride R + 1 in LDS, so the rows a wave
-// reads fall in different banks) and W; thread (g, c8) computes rows
-// 4g .. 4g+3 and columns 8 c8 .. 8 c8 + 7 from registers.
-__global__ void __launch_bounds__(256) als_solve(const float* M, const float* W, float* A, int64_t rows, int R,
+// A = M W for a rows x R fp32 matrix M and an R x R fp64 matrix W, with the
+// products and sums in fp64 and A rounded to fp32 once.  W = V^{-1} D^{-1}
+// has large entries of opposite sign when V is ill-conditioned (nearly
+// collinear factor columns), and the sum over k then cancels: fp32 sums
+// would lose about log2(cancellation) bits, fp64 sums keep the result
+// accurate to fp32 rounding.  A block of 256 threads stages RB rows of M
+// (row stride R + 1 in LDS, so the rows a wave reads fall in different
+// banks) and W; thread (g, c8) computes RPT rows and 8 columns from registers.
+template <int RPT>
+__global__ void __launch_bounds__(256) als_solve(const float* M, const double* W, float* A, int64_t rows, int R,
                                                  int RB)
 {
-    extern __shared__ __align__(16) float s_solve[];
+    extern __shared__ __align__(16) double s_solve[];
     const int C8 = (R + 7) / 8;                 // column groups of 8
     const int RW = 8 * C8;                      // padded row length of W
-    float* sW = s_solve;                        // [R][RW]
-    float* sM = s_solve + R * RW;               // [RB][R + 1]
+    double* sW = s_solve;                       // [R][RW]
+    float* sM = reinterpret_cast<float*>(s_solve + R * RW);   // [RB][R + 1]
     const int tid = threadIdx.x;
     for (int e = tid; e < R * RW; e += 256) {
         const int k = e / RW, c = e % RW;
-        sW[e] = c < R ? W[k * R + c] : 0.f;
+        sW[e] = c < R ? W[k * R + c] : 0.0;
     }
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int nr = (int)std::min<int64_t>(RB, rows - r0);
     if ((R & 3) == 0) {
-        // 8 loads per thread in flight before their LDS stores (a full block is
-        // exactly 8 float4 per thread when R is a multiple of 8)
+        // 8 loads per thread in flight before their LDS stores
         const float4* M4 = reinterpret_cast<const float4*>(M + r0 * R);
         const int n4 = nr * R / 4;
         for (int base = 0; base < n4; base += 8 * 256) {
@@ -345,35 +349,41 @@ __global__ void __launch_bounds__(256) als_solve(const float* M, const float* W,
     }
     __syncthreads();
     const int g = tid / C8, c8 = tid % C8;
-    const int i0 = 4 * g;
+    const int i0 = RPT * g;
     if (i0 >= nr) return;
-    float acc[4][8];
+    double acc[RPT][8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < RPT; ++j)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[j][c] = 0.f;
+        for (int c = 0; c < 8; ++c) acc[j][c] = 0.0;
     for (int k = 0; k < R; ++k) {
-        const float4 w0 = *reinterpret_cast<const float4*>(&sW[k * RW + 8 * c8]);
-        const float4 w1 = *reinterpret_cast<const float4*>(&sW[k * RW + 8 * c8 + 4]);
-        const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        double w[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float m = (i0 + j < nr) ? sM[(i0 + j) * (R + 1) + k] : 0.f;
+        for (int c = 0; c < 8; c += 2) {
+            const double2 x = *reinterpret_cast<const double2*>(&sW[k * RW + 8 * c8 + c]);
+            w[c] = x.x;
+            w[c + 1] = x.y;
+        }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[j][c] = fmaf(m, w[c], acc[j][c]);
+        for (int j = 0; j < RPT; ++j) {
+            const double m = (i0 + j < nr) ? (double)sM[(i0 + j) * (R + 1) + k] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[j][c] = fma(m, w[c], acc[j][c]);
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < RPT; ++j) {
         if (i0 + j >= nr) continue;
         float* out = A + (r0 + i0 + j) * R + 8 * c8;
         if ((R & 7) == 0) {   // 32-byte aligned run of 8 columns
-            *reinterpret_cast<float4*>(out) = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
-            *reinterpret_cast<float4*>(out + 4) = make_float4(acc[j][4], acc[j][5], acc[j][6], acc[j][7]);
+            *reinterpret_cast<float4*>(out) = make_float4((float)acc[j][0], (float)acc[j][1], (float)acc[j][2],
+                                                          (float)acc[j][3]);
+            *reinterpret_cast<float4*>(out + 4) = make_float4((float)acc[j][4], (float)acc[j][5], (float)acc[j][6],
+                                                              (float)acc[j][7]);
         } else {
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (8 * c8 + c < R) out[c] = acc[j][c];
+                if (8 * c8 + c < R) out[c] = (float)acc[j][c];
         }
     }
 }
@@ -486,7 +496,7 @@ hipError_t launch_gram_noalloc(const float* A, int64_t rows, int R, double* G, h
     return launch_gram(A, rows, R, ptr, G, st, nslab);
 }
 
-hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, float* W,
+hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, double* W,
                             double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st)
 {
     const size_t bytes = (size_t)4 * R * R * sizeof(double);
@@ -496,13 +506,18 @@ hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, dou
     return hipGetLastError();
 }
 
-hipError_t launch_als_solve(const float* M, const float* W, float* A, int64_t rows, int R, hipStream_t st)
+hipError_t launch_als_solve(const float* M, const double* W, float* A, int64_t rows, int R, hipStream_t st)
 {
     if (rows <= 0) return hipSuccess;
     const int C8 = (R + 7) / 8;
-    const int RB = 4 * (256 / C8);     // rows per block: every thread owns 4 rows x 8 columns
-    const size_t lds = (size_t)(R * 8 * C8 + RB * (R + 1)) * sizeof(float);
-    hipLaunchKernelGGL(als_solve, dim3((unsigned)((rows + RB - 1) / RB)), dim3(256), lds, st, M, W, A, rows, R, RB);
+    // rows per thread: 4, or 2 above R = 64 so that the fp64 W (R x 8 C8
+    // doubles) and the staged rows of M fit one block's LDS
+    const int rpt = R > 64 ? 2 : 4;
+    const int RB = rpt * (256 / C8);    // rows per block
+    const size_t lds = (size_t)R * 8 * C8 * sizeof(double) + (size_t)RB * (R + 1) * sizeof(float);
+    const dim3 grid((unsigned)((rows + RB - 1) / RB));
+    if (rpt == 4) hipLaunchKernelGGL(als_solve<4>, grid, dim3(256), lds, st, M, W, A, rows, R, RB);
+    else hipLaunchKernelGGL(als_solve<2>, grid, dim3(256), lds, st, M, W, A, rows, R, RB);
     return hipGetLastError();
 }
 

@@ -100,7 +100,7 @@ struct amped_tensor_s {
         double* S = nullptr;       // R x R, M^T M
         float* partial = nullptr;  // Gram partials
         double* scratch = nullptr; // 4 R x R
-        float* W = nullptr;        // R x R
+        double* W = nullptr;       // R x R, V^{-1} D^{-1}
         double* xnorm2 = nullptr;  // ||X||^2 (computed once)
         bool have_xnorm2 = false;
         bool have_grams = false;   // G matches the factors the last sweep wrote
@@ -840,8 +840,8 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
         w.partial = static_cast<float*>(p);
         if ((e = t->alloc(&p, 4 * RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
         w.scratch = static_cast<double*>(p);
-        if ((e = t->alloc(&p, RR * sizeof(float))) != hipSuccess) return hip_fail(e, "als workspace");
-        w.W = static_cast<float*>(p);
+        if ((e = t->alloc(&p, RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.W = static_cast<double*>(p);
         if (!w.xnorm2) {
             if ((e = t->alloc(&p, sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
             w.xnorm2 = static_cast<double*>(p);
