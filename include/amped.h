@@ -223,6 +223,21 @@ amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float *co
                            float scale, float *grad, void *stream);
 
 /*
+ * amped_cp_grad and amped_cp_loss in one pass over the layout of `mode` (the
+ * CP model of Sec. 2.1 and the gradient of its loss): every mode's layout
+ * holds every stored entry, so the residuals e(k) the gradient recomputes
+ * also give the loss.  A training step that needs the loss and every
+ * factor's gradient then reads the tensor N times instead of N + 1.
+ *   grad   as in amped_cp_grad (the same bits)
+ *   loss   DEVICE, one double, overwritten with sum_k e(k)^2 (fp64 sum of
+ *          fp32 per-entry residuals; the entries are added in the order of
+ *          this mode's layout, so the last bits may differ from amped_cp_loss)
+ * Errors as in amped_cp_grad; INVALID also for a NULL loss.
+ */
+amped_status amped_cp_loss_grad(amped_tensor_t t, int mode, int rank, const float *const *factors,
+                                float scale, float *grad, double *loss, void *stream);
+
+/*
  * Gram matrix G = A^T A of a dense matrix, the R x R building block of the
  * CP-ALS update (V = Hadamard product of the other factors' Gram matrices).
  * Products on the matrix cores in fp32, per-slab partial sums added in fp64

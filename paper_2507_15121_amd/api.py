@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "RANGE", 3: "NOMEM", 4: "HIP", 5: "UNS
 # every symbol declared in include/amped.h
 EXPORTED = ["amped_tensor_create", "amped_tensor_destroy", "amped_tensor_info", "amped_tensor_layout",
             "amped_layout_host", "amped_mttkrp", "amped_mttkrp_bf16", "amped_cp_loss", "amped_cp_grad",
-            "amped_gram", "amped_gram_noalloc", "amped_cp_als_sweep", "amped_last_error", "amped_version"]
+            "amped_cp_loss_grad", "amped_gram", "amped_gram_noalloc", "amped_cp_als_sweep", "amped_last_error", "amped_version"]
 
 
 class AmpedError(RuntimeError):
@@ -57,6 +57,7 @@ def lib():
         L.amped_mttkrp_bf16.argtypes = [vp, i32, i32, pvp, vp, vp]
         L.amped_cp_loss.argtypes = [vp, i32, pvp, vp, vp]
         L.amped_cp_grad.argtypes = [vp, i32, i32, pvp, ctypes.c_float, vp, vp]
+        L.amped_cp_loss_grad.argtypes = [vp, i32, i32, pvp, ctypes.c_float, vp, vp, vp]
         L.amped_gram.argtypes = [vp, i64, i32, vp, vp]
         L.amped_gram_noalloc.argtypes = [vp, i64, i32, vp, vp]
         L.amped_cp_als_sweep.argtypes = [vp, i32, pvp, vp, vp, ctypes.c_uint, vp]
@@ -259,6 +260,22 @@ def cp_grad(t: Tensor, mode: int, factors, scale: float, out=None, stream=None):
     _check(lib().amped_cp_grad(t.handle, int(mode), rank, ptrs, ctypes.c_float(scale),
                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def cp_loss_grad(t: Tensor, mode: int, factors, scale: float, out=None, loss=None, stream=None):
+    """cp_grad() and cp_loss() in one pass over the mode's layout: returns
+    (loss as a 0-dim float64 device tensor, scale * MTTKRP_mode(residuals))."""
+    torch = _torch()
+    ptrs, rank = _ptr_array(t, factors, torch.float32, None)
+    out = _out(t, mode, rank, out, factors[0])
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=factors[0].device)
+    if loss.dtype != torch.float64 or loss.numel() != 1:
+        raise ValueError("loss output must be one float64")
+    _check(lib().amped_cp_loss_grad(t.handle, int(mode), rank, ptrs, ctypes.c_float(scale),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+                                    _stream_ptr(stream)))
+    return loss, out
 
 
 def gram(A, out=None, stream=None):

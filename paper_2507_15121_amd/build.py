@@ -5,6 +5,8 @@
 * ``libamped_synth.so`` -- the seeded input generator (gcc/OpenMP), host only.
 * ``libamped_qstats.so`` -- libamped.so built with AMPED_QUEUE_STATS=1: the
                            load-balance diagnostic (per-wave work-queue records).
+* ``gather_ceiling``    -- a program that times random 128-byte row gathers from a
+                           table of a given size (the GPU's row-gather ceiling).
 
 Every call recompiles.  ``python -m paper_2507_15121_amd.build`` runs it.
 """
@@ -26,9 +28,11 @@ LIB = os.path.join(HERE, "libamped.so")
 SYNTH_LIB = os.path.join(HERE, "libamped_synth.so")
 # load-balance diagnostic build: per-wave work-queue records (include/amped_diag.h)
 QSTATS_LIB = os.path.join(HERE, "libamped_qstats.so")
+# row-gather ceiling of the GPU (a program, not part of the library)
+CEILING_BIN = os.path.join(HERE, "gather_ceiling")
 
-HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_loss.hip", "sort.hip",
-               "als.hip"]
+HIP_SOURCES = ["kernels.hip", "k_mttkrp_f32.hip", "k_mttkrp_bf16.hip", "k_grad.hip", "k_grad_loss.hip", "k_loss.hip",
+               "sort.hip", "als.hip"]
 HOST_SOURCES = ["api.cpp", "layout.cpp"]
 
 HIPCC_FLAGS = [
@@ -84,6 +88,16 @@ def build_amped(verbose=False, extra_hip_flags=(), out=None, build_dir=None, ext
     return lib_path
 
 
+def build_gather_ceiling(verbose=False):
+    """The row-gather ceiling program (csrc/gather_ceiling.hip): the rate at
+    which the GPU returns random 128-byte rows from a table of a given size."""
+    hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+    tmp = CEILING_BIN + ".tmp"
+    _run([hipcc] + HIPCC_FLAGS + ["-o", tmp, os.path.join(CSRC, "gather_ceiling.hip")], verbose)
+    os.replace(tmp, CEILING_BIN)
+    return CEILING_BIN
+
+
 def build_qstats(verbose=False):
     """The load-balance diagnostic variant of libamped.so."""
     flag = ["-DAMPED_QUEUE_STATS=1"]
@@ -95,6 +109,7 @@ def build(verbose=False):
     build_synth(verbose)
     build_amped(verbose)
     build_qstats(verbose)
+    build_gather_ceiling(verbose)
 
 
 if __name__ == "__main__":

@@ -701,11 +701,12 @@ amped_status check_call(amped_tensor_t t, int mode, int rank, const void* const*
 }
 
 amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const* factors, float* out, void* stream,
-                        amped::FactorType ft, amped::Kind kind, float scale)
+                        amped::FactorType ft, amped::Kind kind, float scale, double* loss = nullptr)
 {
-    const bool grad = (kind == amped::Kind::ResidualGrad);
+    const bool grad = (kind != amped::Kind::Mttkrp);
     amped_status st = check_call(t, mode, rank, factors, out, grad, grad ? "grad" : "out");
     if (st != AMPED_OK) return st;
+    if (kind == amped::Kind::ResidualGradLoss && !loss) return fail(AMPED_ERR_INVALID, "loss is NULL");
     DeviceGuard guard(t->device);
     if (!guard.ok) return fail(AMPED_ERR_HIP, "cannot select device %d", t->device);
     amped::LaunchArgs a;
@@ -724,11 +725,15 @@ amped_status run_mttkrp(amped_tensor_t t, int mode, int rank, const void* const*
     a.own_factor = grad ? static_cast<const float*>(factors[mode]) : nullptr;
     a.scale = scale;
     a.out = out;
+    a.loss = loss;
     a.stream = static_cast<hipStream_t>(stream);
-    auto launch = [&](const ModeDev& m, int) -> amped_status {
+    const char* what = kind == amped::Kind::Mttkrp ? "amped_mttkrp"
+                       : kind == amped::Kind::ResidualGrad ? "amped_cp_grad" : "amped_cp_loss_grad";
+    auto launch = [&](const ModeDev& m, int i) -> amped_status {
         a.m = &m;
+        a.loss_accumulate = i > 0;   // later shards add to the loss of the first
         hipError_t e = amped::launch_mttkrp(a);
-        return e == hipSuccess ? AMPED_OK : hip_fail(e, grad ? "amped_cp_grad" : "amped_mttkrp");
+        return e == hipSuccess ? AMPED_OK : hip_fail(e, what);
     };
     if (t->host_layout) return stream_shards(t, mode, t->mode[mode], a.stream, ChunkCut{t->nnz, t->stage_len}, launch);
     return launch(t->mode[mode], 0);
@@ -758,6 +763,14 @@ amped_status amped_cp_grad(amped_tensor_t t, int mode, int rank, const float* co
     g_err.clear();
     return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), grad, stream,
                       amped::FactorType::F32, amped::Kind::ResidualGrad, scale);
+}
+
+amped_status amped_cp_loss_grad(amped_tensor_t t, int mode, int rank, const float* const* factors, float scale,
+                                float* grad, double* loss, void* stream)
+{
+    g_err.clear();
+    return run_mttkrp(t, mode, rank, reinterpret_cast<const void* const*>(factors), grad, stream,
+                      amped::FactorType::F32, amped::Kind::ResidualGradLoss, scale, loss);
 }
 
 amped_status amped_gram(const float* A, int64_t rows, int rank, double* G, void* stream)

@@ -95,7 +95,9 @@ struct ModeDev {
 };
 
 enum class FactorType { F32 = 0, BF16 = 1 };
-enum class Kind { Mttkrp = 0, ResidualGrad = 1 };
+// ResidualGradLoss: the residual gradient that also sums the squared
+// residuals into `loss` (the sparse CP loss) in the same pass.
+enum class Kind { Mttkrp = 0, ResidualGrad = 1, ResidualGradLoss = 3 };
 
 struct LaunchArgs {
     const ModeDev* m = nullptr;
@@ -109,6 +111,8 @@ struct LaunchArgs {
     const float* own_factor = nullptr;             // factor of the output mode (ResidualGrad)
     float scale = 1.0f;                            // ResidualGrad output scale
     float* out = nullptr;
+    double* loss = nullptr;                        // ResidualGradLoss: fp64 loss
+    bool loss_accumulate = false;                  // add to *loss instead of resetting it
     hipStream_t stream = nullptr;
 };
 

@@ -372,7 +372,8 @@ struct ChunkQueue {
 // recomputed per nonzero from all factor rows.  KIND 2: the sparse CP loss,
 // sum over nonzeros of (val - CP model)^2 (per-entry work in fp32, each
 // squared residual added in fp64, one fp64 atomic per wave; no output
-// matrix).
+// matrix).  KIND 3: KIND 1 and KIND 2 in one pass (every mode's layout holds
+// every nonzero, so the residuals the gradient computes give the loss too).
 //
 // Memory accesses are software-pipelined:
 //  * the nonzero metadata of tile tau+2 is loaded (VGPRs) while tile tau is
@@ -398,6 +399,8 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     // in flight per batch
     constexpr int U = (KIND != 2 && NIN <= AMPED_UMAX_NIN) ? (KIND == 0 ? AMPED_UMAX : AMPED_UMAX_GRAD)
                                                           : AMPED_UMAX_OWN;
+    constexpr bool GRAD = KIND == 1 || KIND == 3;                // residual gradient: output scaled by p.scale
+    constexpr bool LOSS = KIND == 2 || KIND == 3;                // squared residuals summed into p.loss
     constexpr int TS = (4 * LPR > 2 * U) ? 4 * LPR : 2 * U;      // nonzeros per group per tile
     constexpr int Q4 = TS / (4 * LPR);                           // 16-byte metadata loads per lane and field
     constexpr int NB = TS / U;                                   // batches per tile (even)
@@ -428,14 +431,14 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
     const int64_t ld = VEC ? (int64_t)RT : p.ld;
     const uint64_t rb = (uint64_t)ld * sizeof(T);
     const uint64_t rb_own = (uint64_t)ld * sizeof(float);
-    const float oscale = (KIND == 1) ? p.scale : 1.0f;
+    const float oscale = GRAD ? p.scale : 1.0f;
     const char* lbase[NIN];
 #pragma unroll
     for (int w = 0; w < NIN; ++w) lbase[w] = static_cast<const char*>(p.fac[w]) + (int64_t)c * sizeof(T);
     const char* obase = OWN ? reinterpret_cast<const char*>(p.own + c) : nullptr;
     const char* zrow = static_cast<const char*>(p.zero_row);
     float* const gsink = p.sink + s * RPL;
-    double lsum = 0.0;  // KIND 2: sum of squared residuals (each group's value in all its LPR lanes)
+    double lsum = 0.0;  // LOSS: sum of squared residuals (each group's value in all its LPR lanes)
     // BUF: every factor is below 4 GiB, so rows are read with buffer loads
     // addressed by a 32-bit byte offset (row * row_bytes + column bytes)
     __amdgpu_buffer_rsrc_t rsrc[NIN];
@@ -727,9 +730,8 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
                     if constexpr (!VEC) part = lane_on ? part : 0.f;
                     coef = val - group_sum<LPR>(part);
                 }
-                if constexpr (KIND == 2) {
-                    lsum = fma((double)coef, (double)coef, lsum);
-                } else {
+                if constexpr (LOSS) lsum = fma((double)coef, (double)coef, lsum);
+                if constexpr (OUT) {
                     if (key[ju] != open_key) {
                         flush();
 #pragma unroll
@@ -864,7 +866,7 @@ __global__ void __launch_bounds__(mttkrp_block(KIND)) AMPED_OCCUPANCY mttkrp_ker
         r[3] = (unsigned long long)wall_clock64();
     }
 #endif
-    if constexpr (KIND == 2) {
+    if constexpr (LOSS) {
         // wave sum in fp64, one atomic per wave.  The first log2(LPR) steps add
         // equal values (every lane of a group holds the group's sum), so they
         // are exact doublings undone by the final 1/LPR.
@@ -886,6 +888,7 @@ KernelFn pick_mttkrp_f32(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_mttkrp_bf16(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_grad(int nin, int lpr, bool scalar, bool buf);
 KernelFn pick_loss(int nin, int lpr, bool scalar, bool buf);
+KernelFn pick_grad_loss(int nin, int lpr, bool scalar, bool buf);
 
 // The instance each picker returns: lpr counts 16-byte lanes per row (the
 // vector path), scalar selects the column-tile path.  bfloat16 rows of up to

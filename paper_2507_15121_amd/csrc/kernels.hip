@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(kBlock) permute_kernel(uint32_t* dst, const ui
 KernelFn pick_mttkrp(int nin, FactorType ft, Kind kind, int lpr, bool scalar, bool buf)
 {
     if (kind == Kind::ResidualGrad) return ft == FactorType::F32 ? pick_grad(nin, lpr, scalar, buf) : nullptr;
+    if (kind == Kind::ResidualGradLoss) return ft == FactorType::F32 ? pick_grad_loss(nin, lpr, scalar, buf) : nullptr;
     return ft == FactorType::F32 ? pick_mttkrp_f32(nin, lpr, scalar, buf) : pick_mttkrp_bf16(nin, lpr, scalar, buf);
 }
 
@@ -269,12 +270,13 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
     bool buf = AMPED_BUFFER_LOADS != 0;
     for (int w = 0; w < a.nin; ++w)
         if (!fits_buffer(a.in_rows[w], a.rank, eb)) buf = false;
-    if (a.kind == Kind::ResidualGrad && !fits_buffer(m.rows, a.rank, 4)) buf = false;
+    const bool grad = a.kind != Kind::Mttkrp;   // the residual forms read the output mode's factor
+    if (grad && !fits_buffer(m.rows, a.rank, 4)) buf = false;
     KernelFn fn = lpr ? pick_mttkrp(a.nin, a.ftype, a.kind, lpr, false, buf) : nullptr;
     const bool scalar = (fn == nullptr);
     // the fused residual form needs the whole row in one launch (rank <= 64
     // on the scalar path)
-    if (scalar && a.kind == Kind::ResidualGrad && a.rank > 64) return hipErrorNotSupported;
+    if (scalar && grad && a.rank > 64) return hipErrorNotSupported;
     if (scalar) fn = pick_mttkrp(a.nin, a.ftype, a.kind, 64, true, false);
     if (!fn) return hipErrorNotSupported;
     KParams k = base_params(m);
@@ -283,8 +285,9 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
         k.fbytes[w] = buf ? (uint32_t)((uint64_t)a.in_rows[w] * a.rank * eb) : 0u;
     }
     k.own = a.own_factor;
-    k.own_bytes = (buf && a.kind == Kind::ResidualGrad) ? (uint32_t)((uint64_t)m.rows * a.rank * 4) : 0u;
+    k.own_bytes = (buf && grad) ? (uint32_t)((uint64_t)m.rows * a.rank * 4) : 0u;
     k.out = a.out;
+    k.loss = a.kind == Kind::ResidualGradLoss ? a.loss : nullptr;
     k.ld = a.rank;
     k.scale = a.scale;
     const int block = mttkrp_block(a.kind == Kind::Mttkrp ? 0 : 1);
@@ -294,7 +297,9 @@ hipError_t launch_mttkrp(const LaunchArgs& a)
     const int tile = scalar ? 64 : a.rank;
     for (int col0 = 0; col0 < a.rank; col0 += tile) {
         const int ncols = std::min(tile, a.rank - col0);
-        hipError_t e = launch_init(m, a.out, a.rank, col0, ncols, nullptr, a.stream);
+        // the loss (one launch: the residual forms never tile columns) is reset
+        // by the init kernel unless this launch adds to it
+        hipError_t e = launch_init(m, a.out, a.rank, col0, ncols, a.loss_accumulate ? nullptr : k.loss, a.stream);
         if (e != hipSuccess) return e;
         if (m.n_chunks == 0) continue;
         k.col0 = col0;

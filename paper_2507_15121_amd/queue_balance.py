@@ -76,10 +76,14 @@ def main():
     lib_path = os.path.join(_HERE, "libamped_qstats.so")
     if not os.path.exists(lib_path):
         sys.exit("libamped_qstats.so is not built (paper_2507_15121_amd.build.build_qstats)")
-    os.environ["AMPED_LIB"] = lib_path
     import torch
 
     from paper_2507_15121_amd import api, synth
+    # the package import has already read AMPED_LIB; point the binding at the
+    # diagnostic build before its first call loads a library
+    if api._lib is not None:
+        sys.exit("the C library is already loaded")
+    api.LIB_PATH = lib_path
     torch.cuda.set_device(0)
     wl = synth.WORKLOADS[args.workload]
     t0 = time.time()

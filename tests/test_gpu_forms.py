@@ -14,7 +14,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2507_15121_amd import api, synth  # noqa: E402
-from paper_2507_15121_amd.autograd import SparseCPLoss  # noqa: E402
+from paper_2507_15121_amd.autograd import SparseCPLoss, SparseCPLossFused, sparse_cp_loss  # noqa: E402
 
 
 # ------------------------------------------------------------------ bfloat16
@@ -132,6 +132,82 @@ def test_directional_finite_difference():
     fd = (float(api.cp_loss(t, plus)) - float(api.cp_loss(t, minus))) / (2 * eps)
     log("directional derivative %.6e, central difference %.6e" % (dirderiv, fd))
     assert abs(fd - dirderiv) <= 1e-3 * abs(dirderiv)
+    t.close()
+
+
+@pytest.mark.parametrize("dims,rank", [((3000, 2000, 500, 100), 32), ((2000, 1500, 800), 16),
+                                       ((500, 400, 300), 64), ((400, 300, 200), 5)])
+def test_cp_loss_grad_one_pass_vs_oracle(dims, rank):
+    """amped_cp_loss_grad for every mode (vector path at 16, 32 and 64, the
+    column-tile path at 5): the gradient against the FP64 oracle gradient and
+    the loss, summed in that mode's order, against the oracle loss, both at
+    1e-5 relative."""
+    st, factors = _problem(dims, 40000, rank, seed=rank + 100, hot=0.05)
+    t = api.Tensor(st.idx, st.val, dims, chunk_nnz=256)
+    dfac = dev_factors(factors)
+    ref_loss, _ = oracle.cp_loss(st.idx, st.val, factors)
+    for d in range(len(dims)):
+        loss, g = api.cp_loss_grad(t, d, dfac, -2.0 * 0.75)
+        ref = oracle.cp_grad(st.idx, st.val, dims, factors, d, grad_out=0.75)
+        e, el = rel(g.cpu().numpy(), ref), abs(float(loss) - ref_loss) / abs(ref_loss)
+        log("loss+grad mode %d: grad rel %.2e, loss rel %.2e" % (d, e, el))
+        assert e <= 1e-5 and el <= 1e-5
+    t.close()
+
+
+def test_cp_loss_grad_integer_exact_equals_separate_calls():
+    """Small integers (values 1..4, factors -2..2): every residual, product and
+    partial sum is exact, so the one-pass gradient equals amped_cp_grad's and
+    the oracle's bit for bit, and the loss equals amped_cp_loss's and the
+    oracle's exactly, for every mode, also when called again on the same
+    outputs."""
+    rng = np.random.default_rng(31)
+    dims = (3000, 1500, 700)
+    st = synth.tensor(dims, 40000, "zipf", 1.2, 0.1, seed=31)
+    val = rng.integers(1, 5, st.nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, (d, 32)).astype(np.float32) for d in dims]
+    t = api.Tensor(st.idx, val, dims, chunk_nnz=64)
+    dfac = dev_factors(factors)
+    ref_loss, _ = oracle.cp_loss(st.idx, val, factors)
+    sep_loss = float(api.cp_loss(t, dfac))
+    assert sep_loss == ref_loss
+    loss = torch.full((), float("nan"), dtype=torch.float64, device="cuda")
+    for d in range(3):
+        g = torch.full((dims[d], 32), float("nan"), device="cuda")
+        for _ in range(2):
+            api.cp_loss_grad(t, d, dfac, -2.0, out=g, loss=loss)
+            torch.cuda.synchronize()
+            assert float(loss) == ref_loss
+            ref = oracle.cp_grad(st.idx, val, dims, factors, d).astype(np.float32)
+            np.testing.assert_array_equal(g.cpu().numpy(), ref)
+            np.testing.assert_array_equal(g.cpu().numpy(), api.cp_grad(t, d, dfac, -2.0).cpu().numpy())
+    t.close()
+
+
+def test_fused_autograd_forward_keeps_one_gradient():
+    """sparse_cp_loss with factors that need gradients takes the one-pass
+    forward (loss and the first needed mode's gradient); the backward pass
+    scales that gradient by dL_out on the device and computes the others.
+    Mode 0 needs no gradient here, so the early gradient is mode 1's; under
+    torch.no_grad() the loss-only form runs."""
+    dims = (2000, 1000, 300, 50)
+    st, factors = _problem(dims, 30000, 32, seed=15)
+    t = api.Tensor(st.idx, st.val, dims)
+    dfac = [f.requires_grad_(w != 0) for w, f in enumerate(dev_factors(factors))]
+    L = sparse_cp_loss(t, *dfac)
+    assert isinstance(L.grad_fn, SparseCPLossFused._backward_cls)
+    ref_loss, _ = oracle.cp_loss(st.idx, st.val, factors)
+    assert abs(float(L) - ref_loss) <= 1e-5 * ref_loss
+    (2.5 * L).backward()
+    assert dfac[0].grad is None
+    for d in (1, 2, 3):
+        ref = oracle.cp_grad(st.idx, st.val, dims, factors, d, grad_out=2.5)
+        e = rel(dfac[d].grad.cpu().numpy(), ref)
+        log("fused autograd grad mode %d rel %.2e" % (d, e))
+        assert e <= 1e-5
+    with torch.no_grad():
+        L2 = sparse_cp_loss(t, *dfac)
+    assert L2.grad_fn is None and abs(float(L2) - ref_loss) <= 1e-5 * ref_loss
     t.close()
 
 

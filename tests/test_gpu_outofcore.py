@@ -92,9 +92,13 @@ def test_streamed_loss_and_grad_vs_oracle():
     assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
     for d in range(4):
         g = api.cp_grad(t, d, dfac, -2.0).cpu().numpy()
-        e = rel(g, oracle.cp_grad(st.idx, st.val, dims, factors, d))
-        log("  streamed grad mode %d rel %.2e" % (d, e))
-        assert e <= 1e-5
+        ref = oracle.cp_grad(st.idx, st.val, dims, factors, d)
+        e = rel(g, ref)
+        # the one-pass form: the loss adds up over the 40 shards of the mode
+        lf, gf = api.cp_loss_grad(t, d, dfac, -2.0)
+        ef, elf = rel(gf.cpu().numpy(), ref), abs(float(lf) - ref_loss) / abs(ref_loss)
+        log("  streamed grad mode %d rel %.2e; one pass: grad rel %.2e, loss rel %.2e" % (d, e, ef, elf))
+        assert e <= 1e-5 and ef <= 1e-5 and elf <= 1e-5
     t.close()
 
 
