@@ -184,12 +184,20 @@ __global__ void __launch_bounds__(256) gram_reduce(const float* partial, int64_t
     }
 }
 
+// Largest 1-norm condition number of V for which the update's product M W
+// keeps fp32 sums (als_solve).  The sum over k of M[i, k] W[k, r] cancels by
+// up to about sqrt(kappa) when V is ill-conditioned (nearly collinear factor
+// columns); fp32 sums then lose that many ulps, so above this bound the sums
+// are taken in fp64.  At kappa = 1e4 the fp32 rounding of M W stays below the
+// fp32 error of M itself (about 1e-6 relative).
+constexpr double kSolveFp32MaxCond = 1e4;
+
 // R x R fp64 algebra of one mode update, one block of 256 threads.  Works
 // in 4 R x R doubles: LDS when they fit (dynamic, in_lds), else the global
 // scratch.  G: [N][R][R] (G[d] is replaced).
 __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int N, int d, int R, double* scratch,
-                                                 double* W, double* lambda, int last, const double* xnorm2,
-                                                 double* fit, int in_lds)
+                                                 double* W, int* wide, double* lambda, int last,
+                                                 const double* xnorm2, double* fit, int in_lds)
 {
     extern __shared__ __align__(16) double s_small[];
     if (in_lds) scratch = s_small;
@@ -240,6 +248,28 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
         }
         __syncthreads();
     }
+    // The 1-norm condition number kappa = ||V||_1 ||V^{-1}||_1 picks the
+    // precision of the update's product M W (als_solve): fp32 sums while kappa
+    // <= kSolveFp32MaxCond, fp64 sums above (or when kappa is not finite).
+    if (tid < 64) {
+        double a = 0.0, b = 0.0;
+        for (int j = tid; j < R; j += 64) {
+            double sa = 0.0, sb = 0.0;
+            for (int i = 0; i < R; ++i) {
+                sa += fabs(V[i * R + j]);
+                sb += fabs(Vi[i * R + j]);
+            }
+            a = fmax(a, sa);
+            b = fmax(b, sb);
+        }
+        for (int m = 1; m < 64; m <<= 1) {
+            a = fmax(a, __shfl_xor(a, m, 64));
+            b = fmax(b, __shfl_xor(b, m, 64));
+        }
+        const double kappa = a * b;
+        if (tid == 0) *wide = (kappa <= kSolveFp32MaxCond) ? 0 : 1;   // NaN: fp64
+    }
+    __syncthreads();
     // S into V's slot (V is no longer needed), then T = S V^{-1}
     for (int e = tid; e < RR; e += 256) V[e] = S[e];
     __syncthreads();
@@ -299,27 +329,68 @@ __global__ void __launch_bounds__(256) als_small(double* G, const double* S, int
     }
 }
 
-// A = M W for a rows x R fp32 matrix M and an R x R fp64 matrix W, with the
-// products and sums in fp64 and A rounded to fp32 once.  W = V^{-1} D^{-1}
-// has large entries of opposite sign when V is ill-conditioned (nearly
-// collinear factor columns), and the sum over k then cancels: fp32 sums
-// would lose about log2(cancellation) bits, fp64 sums keep the result
-// accurate to fp32 rounding.  A block of 256 threads stages RB rows of M
-// (row stride R + 1 in LDS, so the rows a wave reads fall in different
-// banks) and W; thread (g, c8) computes RPT rows and 8 columns from registers.
+// A = M W for a rows x R fp32 matrix M and an R x R fp64 matrix W.  W =
+// V^{-1} D^{-1} has large entries of opposite sign when V is ill-conditioned
+// (nearly collinear factor columns), and the sum over k then cancels: when
+// als_small flagged V (*wide != 0) the products and sums are fp64 and A is
+// rounded to fp32 once, otherwise W is rounded to fp32 and the sums are fp32.
+// A block of 256 threads stages RB rows of M (row stride R + 1 in LDS, so the
+// rows a wave reads fall in different banks) and W; thread (g, c8) computes
+// RPT rows and 8 columns from registers.
+template <int RPT, typename Acc>
+__device__ __forceinline__ void solve_tile(const Acc* sW, int RW, const float* sM, int R, int i0, int nr, int c8,
+                                           float* A, int64_t r0)
+{
+    Acc acc[RPT][8];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[j][c] = Acc(0);
+    for (int k = 0; k < R; ++k) {
+        Acc w[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) w[c] = sW[k * RW + 8 * c8 + c];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const Acc m = (i0 + j < nr) ? (Acc)sM[(i0 + j) * (R + 1) + k] : Acc(0);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[j][c] = fma(m, w[c], acc[j][c]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (i0 + j >= nr) continue;
+        float* out = A + (r0 + i0 + j) * R + 8 * c8;
+        if ((R & 7) == 0) {   // 32-byte aligned run of 8 columns
+            *reinterpret_cast<float4*>(out) = make_float4((float)acc[j][0], (float)acc[j][1], (float)acc[j][2],
+                                                          (float)acc[j][3]);
+            *reinterpret_cast<float4*>(out + 4) = make_float4((float)acc[j][4], (float)acc[j][5], (float)acc[j][6],
+                                                              (float)acc[j][7]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (8 * c8 + c < R) out[c] = (float)acc[j][c];
+        }
+    }
+}
+
 template <int RPT>
-__global__ void __launch_bounds__(256) als_solve(const float* M, const double* W, float* A, int64_t rows, int R,
-                                                 int RB)
+__global__ void __launch_bounds__(256) als_solve(const float* M, const double* W, const int* wide_flag, float* A,
+                                                 int64_t rows, int R, int RB)
 {
     extern __shared__ __align__(16) double s_solve[];
     const int C8 = (R + 7) / 8;                 // column groups of 8
     const int RW = 8 * C8;                      // padded row length of W
-    double* sW = s_solve;                       // [R][RW]
+    const bool wide = *wide_flag != 0;          // the same for every thread
+    double* sW = s_solve;                       // [R][RW] fp64, or fp32 in the first half
+    float* sWf = reinterpret_cast<float*>(s_solve);
     float* sM = reinterpret_cast<float*>(s_solve + R * RW);   // [RB][R + 1]
     const int tid = threadIdx.x;
     for (int e = tid; e < R * RW; e += 256) {
         const int k = e / RW, c = e % RW;
-        sW[e] = c < R ? W[k * R + c] : 0.0;
+        const double w = c < R ? W[k * R + c] : 0.0;
+        if (wide) sW[e] = w;
+        else sWf[e] = (float)w;
     }
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int nr = (int)std::min<int64_t>(RB, rows - r0);
@@ -351,41 +422,8 @@ __global__ void __launch_bounds__(256) als_solve(const float* M, const double* W
     const int g = tid / C8, c8 = tid % C8;
     const int i0 = RPT * g;
     if (i0 >= nr) return;
-    double acc[RPT][8];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[j][c] = 0.0;
-    for (int k = 0; k < R; ++k) {
-        double w[8];
-#pragma unroll
-        for (int c = 0; c < 8; c += 2) {
-            const double2 x = *reinterpret_cast<const double2*>(&sW[k * RW + 8 * c8 + c]);
-            w[c] = x.x;
-            w[c + 1] = x.y;
-        }
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const double m = (i0 + j < nr) ? (double)sM[(i0 + j) * (R + 1) + k] : 0.0;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc[j][c] = fma(m, w[c], acc[j][c]);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        if (i0 + j >= nr) continue;
-        float* out = A + (r0 + i0 + j) * R + 8 * c8;
-        if ((R & 7) == 0) {   // 32-byte aligned run of 8 columns
-            *reinterpret_cast<float4*>(out) = make_float4((float)acc[j][0], (float)acc[j][1], (float)acc[j][2],
-                                                          (float)acc[j][3]);
-            *reinterpret_cast<float4*>(out + 4) = make_float4((float)acc[j][4], (float)acc[j][5], (float)acc[j][6],
-                                                              (float)acc[j][7]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (8 * c8 + c < R) out[c] = (float)acc[j][c];
-        }
-    }
+    if (wide) solve_tile<RPT, double>(sW, RW, sM, R, i0, nr, c8, A, r0);
+    else solve_tile<RPT, float>(sWf, RW, sM, R, i0, nr, c8, A, r0);
 }
 
 // ||X||^2 over a layout whose exact duplicates are adjacent (mode 0's).
@@ -496,17 +534,18 @@ hipError_t launch_gram_noalloc(const float* A, int64_t rows, int R, double* G, h
     return launch_gram(A, rows, R, ptr, G, st, nslab);
 }
 
-hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, double* W,
+hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, double* W, int* wide,
                             double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st)
 {
     const size_t bytes = (size_t)4 * R * R * sizeof(double);
     const bool in_lds = bytes <= (size_t)128 * 1024;
-    hipLaunchKernelGGL(als_small, dim3(1), dim3(256), in_lds ? bytes : 0, st, G, S, N, d, R, scratch, W, lambda,
-                       last ? 1 : 0, xnorm2, fit, in_lds ? 1 : 0);
+    hipLaunchKernelGGL(als_small, dim3(1), dim3(256), in_lds ? bytes : 0, st, G, S, N, d, R, scratch, W, wide,
+                       lambda, last ? 1 : 0, xnorm2, fit, in_lds ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_als_solve(const float* M, const double* W, float* A, int64_t rows, int R, hipStream_t st)
+hipError_t launch_als_solve(const float* M, const double* W, const int* wide, float* A, int64_t rows, int R,
+                            hipStream_t st)
 {
     if (rows <= 0) return hipSuccess;
     const int C8 = (R + 7) / 8;
@@ -516,8 +555,8 @@ hipError_t launch_als_solve(const float* M, const double* W, float* A, int64_t r
     const int RB = rpt * (256 / C8);    // rows per block
     const size_t lds = (size_t)R * 8 * C8 * sizeof(double) + (size_t)RB * (R + 1) * sizeof(float);
     const dim3 grid((unsigned)((rows + RB - 1) / RB));
-    if (rpt == 4) hipLaunchKernelGGL(als_solve<4>, grid, dim3(256), lds, st, M, W, A, rows, R, RB);
-    else hipLaunchKernelGGL(als_solve<2>, grid, dim3(256), lds, st, M, W, A, rows, R, RB);
+    if (rpt == 4) hipLaunchKernelGGL(als_solve<4>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB);
+    else hipLaunchKernelGGL(als_solve<2>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB);
     return hipGetLastError();
 }
 

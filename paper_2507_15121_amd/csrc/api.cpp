@@ -101,6 +101,7 @@ struct amped_tensor_s {
         float* partial = nullptr;  // Gram partials
         double* scratch = nullptr; // 4 R x R
         double* W = nullptr;       // R x R, V^{-1} D^{-1}
+        int* wide = nullptr;       // set by als_small: the product M W sums in fp64
         double* xnorm2 = nullptr;  // ||X||^2 (computed once)
         bool have_xnorm2 = false;
         bool have_grams = false;   // G matches the factors the last sweep wrote
@@ -832,7 +833,8 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
     hipError_t e = hipSuccess;
     const size_t RR = (size_t)rank * rank;
     if (w.rank != rank) {
-        for (void* q : {(void*)w.M, (void*)w.G, (void*)w.S, (void*)w.partial, (void*)w.scratch, (void*)w.W})
+        for (void* q : {(void*)w.M, (void*)w.G, (void*)w.S, (void*)w.partial, (void*)w.scratch, (void*)w.W,
+                        (void*)w.wide})
             if (q) t->release(q);
         double* keep_x = w.xnorm2;
         const bool keep_have = w.have_xnorm2;
@@ -855,6 +857,8 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
         w.scratch = static_cast<double*>(p);
         if ((e = t->alloc(&p, RR * sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
         w.W = static_cast<double*>(p);
+        if ((e = t->alloc(&p, sizeof(int))) != hipSuccess) return hip_fail(e, "als workspace");
+        w.wide = static_cast<int*>(p);
         if (!w.xnorm2) {
             if ((e = t->alloc(&p, sizeof(double))) != hipSuccess) return hip_fail(e, "als workspace");
             w.xnorm2 = static_cast<double*>(p);
@@ -901,10 +905,10 @@ amped_status amped_cp_als_sweep(amped_tensor_t t, int rank, float* const* factor
         if (st != AMPED_OK) return st;
         if ((e = amped::launch_gram(w.M, t->dims[d], rank, w.partial, w.S, s)) != hipSuccess)
             return hip_fail(e, "gram");
-        if ((e = amped::launch_als_small(w.G, w.S, N, d, rank, w.scratch, w.W, lambda, d == N - 1, w.xnorm2, fit,
-                                         s)) != hipSuccess)
+        if ((e = amped::launch_als_small(w.G, w.S, N, d, rank, w.scratch, w.W, w.wide, lambda, d == N - 1,
+                                         w.xnorm2, fit, s)) != hipSuccess)
             return hip_fail(e, "als update");
-        if ((e = amped::launch_als_solve(w.M, w.W, factors[d], t->dims[d], rank, s)) != hipSuccess)
+        if ((e = amped::launch_als_solve(w.M, w.W, w.wide, factors[d], t->dims[d], rank, s)) != hipSuccess)
             return hip_fail(e, "als solve");
     }
     w.have_grams = true;   // G now holds the Gram matrices of the factors just written

@@ -156,10 +156,12 @@ int64_t gram_noalloc_slabs(int64_t rows, int R);
 hipError_t launch_gram_noalloc(const float* A, int64_t rows, int R, double* G, hipStream_t st);
 // The R x R algebra of the mode-d update (scratch: 4 R x R doubles); G is
 // [N][R][R] and G[d] is replaced by the Gram matrix of the new factor.
-hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, double* W,
+hipError_t launch_als_small(double* G, const double* S, int N, int d, int R, double* scratch, double* W, int* wide,
                             double* lambda, bool last, const double* xnorm2, double* fit, hipStream_t st);
-// A = M W: M and A rows x R fp32, W R x R fp64, products and sums in fp64.
-hipError_t launch_als_solve(const float* M, const double* W, float* A, int64_t rows, int R, hipStream_t st);
+// A = M W: M and A rows x R fp32, W R x R fp64; the sums in fp64 when als_small
+// set *wide (V ill-conditioned), else in fp32.
+hipError_t launch_als_solve(const float* M, const double* W, const int* wide, float* A, int64_t rows, int R,
+                            hipStream_t st);
 // ||X||^2 over a layout whose exact duplicates are adjacent (accumulate: add
 // to *result; no run of duplicates may cross the layout's ends then).
 hipError_t launch_tensor_norm2(const ModeDev& m, int nin, double* result, bool accumulate, hipStream_t st);

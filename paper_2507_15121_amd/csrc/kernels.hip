@@ -42,7 +42,7 @@ namespace amped {
 namespace dev {
 
 // ----------------------------------------------------------------- init kernel
-// Resets the work-queue counter (and the loss) and zeroes the output rows
+// Resets the work-queue counters (and the loss) and zeroes the output rows
 // the MTTKRP kernel does not store: rows that several chunks add into,
 // untouched rows of short runs (both in the zero-row list) and long runs of
 // untouched rows.  vec4: ld, col0 and ncols are multiples of 4 (16-byte stores).
@@ -105,7 +105,7 @@ struct Shape {
 // Work-queue stripes per launch (1..kQueueSlots): AMPED_QUEUE_STRIPES, read
 // once per process, else the default.
 #ifndef AMPED_DEFAULT_STRIPES
-#define AMPED_DEFAULT_STRIPES 1
+#define AMPED_DEFAULT_STRIPES 8
 #endif
 int queue_stripes()
 {

@@ -217,11 +217,12 @@ def _backward_error(A, V, M):
     return float(np.linalg.norm(As @ V - M) / (np.linalg.norm(As) * np.linalg.norm(V, 2) + np.linalg.norm(M)))
 
 
-@pytest.mark.parametrize("delta", [1e-2, 1e-3])
+@pytest.mark.parametrize("delta", [1e-1, 1e-2, 1e-3])
 def test_nearly_collinear_columns_tolerance_scaled_by_condition(delta):
     """Modes 1 and 2 start with column 1 = column 0 + delta * noise, so the
-    mode-0 system V = (A_1^T A_1) * (A_2^T A_2) is nearly singular (cond(V)
-    about 2e4 and 2e6).  The update A_0 = M V^{-1} amplifies the fp32 errors of
+    mode-0 system V = (A_1^T A_1) * (A_2^T A_2) is ill-conditioned (cond(V)
+    about 2e2, 2e4 and 2e6; the update sums M W in fp32 at the first and in
+    fp64 at the other two, whose 1-norm condition exceeds 1e4).  The update A_0 = M V^{-1} amplifies the fp32 errors of
     M and V (about 1e-6 relative) by up to cond(V), so the GPU's mode-0 factor
     is compared with the oracle's at max(1e-4, 1e-6 cond(V)) where that bound
     says something (below 0.5).  Whatever the conditioning, a backward-stable
@@ -251,9 +252,10 @@ def test_nearly_collinear_columns_tolerance_scaled_by_condition(delta):
     tol = max(1e-4, 1e-6 * cond)
     eta = _backward_error(F[0].astype(np.float64), V, M)
     eta_ref = _backward_error(Fo[0], V, M)
-    log("ALS delta=%g: cond(V_0) %.2e, mode-0 factor rel %.2e (bound %.2e), backward error %.2e "
-        "(oracle's own %.2e), fit %.6f vs %.6f" % (delta, cond, e0, tol, eta, eta_ref, float(fit.item()), fo))
-    assert cond > 1e4, "the test must exercise an ill-conditioned V"
+    log("ALS delta=%g: cond(V_0) %.2e (1-norm %.2e), mode-0 factor rel %.2e (bound %.2e), backward error %.2e "
+        "(oracle's own %.2e), fit %.6f vs %.6f" % (delta, cond, np.linalg.cond(V, 1), e0, tol, eta, eta_ref,
+                                                 float(fit.item()), fo))
+    assert cond > 1e2, "the test must exercise an ill-conditioned V"
     assert all(np.isfinite(f).all() for f in F) and np.isfinite(lam.cpu().numpy()).all()
     if tol < 0.5:
         assert e0 <= tol

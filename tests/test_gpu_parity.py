@@ -150,6 +150,50 @@ def test_long_untouched_row_runs():
     _check_all_modes(idx, val, dims, factors, chunk_nnz=32)
 
 
+@pytest.mark.parametrize("chunk", [1, 7, 64])
+def test_untouched_runs_of_every_length_near_the_kernel_threshold(chunk):
+    """Touched mode-0 rows separated by runs of 1..40 untouched rows (every
+    length on both sides of 16, below which the init kernel zeroes a run row
+    by row from its list and above which as one range), with 1-3 nonzeros per
+    touched row, so runs start at chunk starts, lane-group run starts and
+    inside runs; also a short run before the first and after the last touched
+    row.  Every output
+    starts as NaN: mode 0 must equal the oracle bit for bit on integer inputs
+    (untouched rows exactly 0), resident and streamed in shards of 50
+    nonzeros, for MTTKRP and for the fused gradient (with and without the
+    loss)."""
+    rng = np.random.default_rng(1600 + chunk)
+    rows0, gaps = [5], []
+    while len(rows0) < 400:
+        gaps.append(1 + (len(rows0) * 7) % 40)
+        rows0.append(rows0[-1] + gaps[-1] + 1)
+    I0 = rows0[-1] + 9
+    per = rng.integers(1, 4, len(rows0))
+    i0 = np.repeat(np.asarray(rows0, dtype=np.int32), per)
+    nnz = i0.size
+    dims = (I0, 50, 30)
+    i1 = rng.integers(0, dims[1], nnz).astype(np.int32)
+    i2 = rng.integers(0, dims[2], nnz).astype(np.int32)
+    idx = np.stack([i0, i1, i2])
+    o = np.lexsort(idx[::-1])
+    idx = np.ascontiguousarray(idx[:, o])
+    val = rng.integers(1, 5, nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, (d, 16)).astype(np.float32) for d in dims]
+    ref = oracle_mttkrp(idx, val, dims, factors, 0).astype(np.float32)
+    gref = oracle.cp_grad(idx, val, dims, factors, 0).astype(np.float32)
+    dfac = dev_factors(factors)
+    for kw in ({}, {"host_layout": True, "shard_nnz": 50}):
+        t = _tensor(idx, val, dims, chunk_nnz=chunk, **kw)
+        np.testing.assert_array_equal(hip_mttkrp(t, 0, dfac), ref)
+        g = torch.full((I0, 16), float("nan"), device="cuda")
+        api.cp_grad(t, 0, dfac, -2.0, out=g)
+        np.testing.assert_array_equal(g.cpu().numpy(), gref)
+        g.fill_(float("nan"))
+        api.cp_loss_grad(t, 0, dfac, -2.0, out=g)
+        np.testing.assert_array_equal(g.cpu().numpy(), gref)
+        t.close()
+
+
 def test_duplicates_and_unsorted_input():
     rng = np.random.default_rng(5)
     dims = (300, 200, 100)
