@@ -26,7 +26,12 @@ constexpr int32_t kHotEmpty = -2;
 constexpr int kSinkFloats = 512;
 // The init kernel zeroes untouched output rows: runs at least this long as
 // (start, length) ranges, shorter runs row by row from the zero-row list.
+// A range is one workgroup's work, so longer runs are cut into ranges of
+// about kGapPiece rows (each at least kLongGap): an untouched run of millions
+// of rows (say, the unused tail of an index space) is then spread over the
+// whole grid instead of one workgroup.
 constexpr int kLongGap = 16;
+constexpr int kGapPiece = 2048;
 // Work-queue counters per layout: the chunks are split into at most this many
 // contiguous stripes, each with its own counter (one stripe per XCD).
 constexpr int kQueueSlots = 8;

@@ -65,11 +65,16 @@ __global__ void __launch_bounds__(kBlock) init_kernel(float* out, int64_t ld, in
         if (vec4) *reinterpret_cast<float4*>(out + r * ld + col0 + 4 * j) = make_float4(0.f, 0.f, 0.f, 0.f);
         else out[r * ld + col0 + j] = 0.f;
     }
+    // one (start, length) range per workgroup, at most about kGapPiece rows
     for (int64_t gi = blockIdx.x; gi < n_gaps; gi += gridDim.x) {
         const int64_t start = gaps[2 * gi], len = gaps[2 * gi + 1];
-        const int64_t n = len * ncols;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-            out[(start + i / ncols) * ld + col0 + (i % ncols)] = 0.f;
+        const int64_t n = len * nv;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int64_t r = start + i / nv;
+            const int j = (int)(i % nv);
+            if (vec4) *reinterpret_cast<float4*>(out + r * ld + col0 + 4 * j) = make_float4(0.f, 0.f, 0.f, 0.f);
+            else out[r * ld + col0 + j] = 0.f;
+        }
     }
 }
 

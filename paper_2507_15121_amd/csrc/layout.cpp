@@ -175,6 +175,18 @@ void mode_order(const int64_t* dims, int64_t nnz, const int32_t* idx, const std:
 
 namespace {
 
+// A run of len >= kLongGap untouched rows from `start` as (start, length)
+// ranges of at most about kGapPiece rows each (every one at least kLongGap).
+void push_gap(std::vector<int32_t>& gaps, int64_t start, int64_t len)
+{
+    const int64_t n = (len + kGapPiece - 1) / kGapPiece;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t a = start + len * i / n, b = start + len * (i + 1) / n;
+        gaps.push_back((int32_t)a);
+        gaps.push_back((int32_t)(b - a));
+    }
+}
+
 // Chunk flags, zero-row list, long gaps, hot-row tables and touched count from
 // key(p), the output index at position p of the mode's order.
 template <typename Key>
@@ -211,8 +223,7 @@ void tables_from_keys(int64_t nnz, int64_t rows, int64_t chunk, const Key& key, 
             if (cur != prev) {
                 touched++;
                 if (cur - prev - 1 >= kLongGap) {
-                    tgaps[t].push_back((int32_t)(prev + 1));
-                    tgaps[t].push_back((int32_t)(cur - prev - 1));
+                    push_gap(tgaps[t], prev + 1, cur - prev - 1);
                 } else {
                     for (int64_t r = prev + 1; r < cur; ++r) tlone[t].push_back((int32_t)r);
                 }
@@ -227,13 +238,12 @@ void tables_from_keys(int64_t nnz, int64_t rows, int64_t chunk, const Key& key, 
         lay.zero_rows.insert(lay.zero_rows.end(), tlone[t].begin(), tlone[t].end());
     }
     if (nnz == 0) {
-        lay.gaps.push_back(0);
-        lay.gaps.push_back((int32_t)rows);
+        if (rows >= kLongGap) push_gap(lay.gaps, 0, rows);
+        else for (int64_t r = 0; r < rows; ++r) lay.zero_rows.push_back((int32_t)r);
     } else {
         const int64_t last = key(nnz - 1);
         if (rows - last - 1 >= kLongGap) {
-            lay.gaps.push_back((int32_t)(last + 1));
-            lay.gaps.push_back((int32_t)(rows - last - 1));
+            push_gap(lay.gaps, last + 1, rows - last - 1);
         } else {
             for (int64_t r = last + 1; r < rows; ++r) lay.zero_rows.push_back((int32_t)r);
         }

@@ -133,8 +133,8 @@ static void run_case(const Case& c, uint64_t seed)
         CHECK(lay.gaps.size() % 2 == 0, "gaps not in pairs");
         for (size_t g = 0; g + 1 < lay.gaps.size(); g += 2) {
             const int64_t s = lay.gaps[g], len = lay.gaps[g + 1];
-            CHECK(len >= kLongGap || (s == 0 && len == rows), "gap (%lld, %lld) shorter than %d", (long long)s,
-                  (long long)len, kLongGap);
+            CHECK(len >= kLongGap && len <= kGapPiece + kLongGap, "gap (%lld, %lld) outside [%d, %d]", (long long)s,
+                  (long long)len, kLongGap, kGapPiece + kLongGap);
             for (int64_t r = s; r < s + len; ++r) {
                 CHECK(r >= 0 && r < rows, "gap row out of range");
                 if (r >= 0 && r < rows) cover[r]++;

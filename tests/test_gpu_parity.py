@@ -194,6 +194,32 @@ def test_untouched_runs_of_every_length_near_the_kernel_threshold(chunk):
         t.close()
 
 
+@pytest.mark.parametrize("where", ["head", "tail", "middle"])
+def test_millions_of_untouched_rows_in_one_run(where):
+    """All nonzeros of mode 0 within 1000 consecutive rows of a 3M-row mode,
+    so the rest of the output is one or two untouched runs of millions of
+    rows, which the init kernel zeroes as ranges of about 2048 rows spread
+    over its grid; every output starts as NaN and must match the oracle with
+    the untouched rows exactly 0 (also for the fused gradient)."""
+    rng = np.random.default_rng({"head": 1, "tail": 2, "middle": 3}[where])
+    dims = (3_000_000, 64, 32)
+    lo = {"head": 2_990_000, "tail": 0, "middle": 1_500_000}[where]
+    nnz = 20000
+    idx = np.stack([rng.integers(lo, lo + 1000, nnz), rng.integers(0, dims[1], nnz),
+                    rng.integers(0, dims[2], nnz)]).astype(np.int32)
+    val = rng.integers(1, 5, nnz).astype(np.float32)
+    factors = [rng.integers(-2, 3, (d, 16)).astype(np.float32) for d in dims]
+    t = _tensor(idx, val, dims)
+    dfac = dev_factors(factors)
+    for d in range(3):
+        np.testing.assert_array_equal(hip_mttkrp(t, d, dfac),
+                                      oracle_mttkrp(idx, val, dims, factors, d).astype(np.float32))
+    g = torch.full((dims[0], 16), float("nan"), device="cuda")
+    api.cp_grad(t, 0, dfac, -2.0, out=g)
+    np.testing.assert_array_equal(g.cpu().numpy(), oracle.cp_grad(idx, val, dims, factors, 0).astype(np.float32))
+    t.close()
+
+
 def test_duplicates_and_unsorted_input():
     rng = np.random.default_rng(5)
     dims = (300, 200, 100)
