@@ -213,7 +213,7 @@ def test_fused_autograd_forward_keeps_one_gradient():
 
 # ------------------------------------------------------------- hot-row cache
 
-_NO_CACHE_CHILD = r"""
+_CHILD_RUN = r"""
 import sys, numpy as np, torch
 sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
 from paper_2507_15121_amd import api
@@ -231,11 +231,15 @@ np.savez(sys.argv[3], **out)
 """
 
 
-def test_hot_row_cache_is_bit_exact(tmp_path):
-    """The same launches with the LDS row cache off (AMPED_HOT_MAX=0, read once
-    per process, so in a child process) give bit-identical outputs.  Values
-    and factors are small integers, so every sum is exact in fp32 and the
-    order in which chunk-boundary atomics land cannot change a bit."""
+@pytest.mark.parametrize("var,value", [("AMPED_HOT_MAX", "0"), ("AMPED_QUEUE_STRIPES", "1"),
+                                       ("AMPED_QUEUE_STRIPES", "3")])
+def test_hot_row_cache_and_queue_stripes_are_bit_exact(tmp_path, var, value):
+    """The same launches with the LDS row cache off (AMPED_HOT_MAX=0), or with
+    one global work-queue counter or three stripes instead of the default
+    eight (AMPED_QUEUE_STRIPES; each read once per process, so in a child
+    process) give bit-identical outputs.  Values and factors are small
+    integers, so every sum is exact in fp32 and the order in which chunks are
+    taken and chunk-boundary atomics land cannot change a bit."""
     import os
     import subprocess
     import sys
@@ -254,10 +258,10 @@ def test_hot_row_cache_is_bit_exact(tmp_path):
             mine["%s%d" % ("b" if bf else "f", d)] = hm(t, d, dfac, bf16=bf)
     inp = str(tmp_path / "inputs.npz")
     np.savez(inp, dims=np.array(dims), idx=st.idx, val=val, **{"f%d" % w: f for w, f in enumerate(factors)})
-    path = str(tmp_path / "nocache.npz")
-    env = dict(os.environ, AMPED_HOT_MAX="0")
-    log("child run with AMPED_HOT_MAX=0")
-    r = subprocess.run([sys.executable, "-c", _NO_CACHE_CHILD, root, inp, path], env=env, capture_output=True,
+    path = str(tmp_path / "child.npz")
+    env = dict(os.environ, **{var: value})
+    log("child run with %s=%s" % (var, value))
+    r = subprocess.run([sys.executable, "-c", _CHILD_RUN, root, inp, path], env=env, capture_output=True,
                        text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
     other = np.load(path)
