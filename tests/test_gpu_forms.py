@@ -155,6 +155,31 @@ def test_cp_loss_grad_one_pass_vs_oracle(dims, rank):
     t.close()
 
 
+@pytest.mark.parametrize("dims,rank", [((60, 50), 32), ((14, 12, 10, 9, 8), 16), ((10, 9, 8, 7, 6, 5), 8),
+                                       ((6, 6, 5, 5, 4, 4, 3, 3), 4), ((9, 8, 7, 6, 5, 4), 40)])
+def test_cp_loss_and_gradients_at_orders_2_to_8(dims, rank):
+    """The loss, every mode's gradient and the one-pass loss + gradient at
+    orders 2, 5, 6 and 8 (more than four input modes take the column-tile
+    path) against the FP64 oracle, at 1e-5."""
+    rng = np.random.default_rng(len(dims) * 100 + rank)
+    nnz = min(3000, int(np.prod(dims)) // 2)
+    idx, _ = synth.coords(dims, nnz, "uniform", seed=len(dims))
+    val = rng.uniform(0, 1, nnz).astype(np.float32)
+    factors = [(rng.uniform(-1, 1, (d, rank)) * 0.7).astype(np.float32) for d in dims]
+    t = api.Tensor(idx, val, dims, chunk_nnz=64)
+    dfac = dev_factors(factors)
+    ref_loss, _ = oracle.cp_loss(idx, val, factors)
+    assert abs(float(api.cp_loss(t, dfac)) - ref_loss) <= 1e-5 * abs(ref_loss)
+    for d in range(len(dims)):
+        ref = oracle.cp_grad(idx, val, dims, factors, d)
+        e = rel(api.cp_grad(t, d, dfac, -2.0).cpu().numpy(), ref)
+        loss, g = api.cp_loss_grad(t, d, dfac, -2.0)
+        ef, el = rel(g.cpu().numpy(), ref), abs(float(loss) - ref_loss) / abs(ref_loss)
+        log("order %d R=%d mode %d: grad rel %.2e, one pass %.2e, loss rel %.2e" % (len(dims), rank, d, e, ef, el))
+        assert e <= 1e-5 and ef <= 1e-5 and el <= 1e-5
+    t.close()
+
+
 def test_cp_loss_grad_integer_exact_equals_separate_calls():
     """Small integers (values 1..4, factors -2..2): every residual, product and
     partial sum is exact, so the one-pass gradient equals amped_cp_grad's and
@@ -208,6 +233,18 @@ def test_fused_autograd_forward_keeps_one_gradient():
     with torch.no_grad():
         L2 = sparse_cp_loss(t, *dfac)
     assert L2.grad_fn is None and abs(float(L2) - ref_loss) <= 1e-5 * ref_loss
+    # a second backward through the same graph: the kept gradient was used up
+    # by the first, so every gradient is computed again, with the same values
+    L3 = sparse_cp_loss(t, *dfac)
+    for f in dfac:
+        f.grad = None
+    L3.backward(retain_graph=True)
+    first = [None if f.grad is None else f.grad.clone() for f in dfac]
+    for f in dfac:
+        f.grad = None
+    L3.backward()
+    for d in (1, 2, 3):
+        assert rel(dfac[d].grad.cpu().numpy(), first[d].cpu().numpy()) <= 1e-6
     t.close()
 
 
