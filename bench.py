@@ -42,6 +42,21 @@ def measured_traffic(workload, lib_path):
     return None, None
 
 
+def gather_ceiling():
+    """The GPU's measured rate for random 128-byte row gathers that miss the
+    L2 but hit the Infinity Cache (the fastest an L2 miss returns), from the
+    committed summary profiles/gather_ceiling_mi355x.md (the `ceiling_GBps:`
+    line), or None."""
+    path = os.path.join(PROFILES, "gather_ceiling_mi355x.md")
+    try:
+        for line in open(path):
+            if line.startswith("ceiling_GBps:"):
+                return float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return None
+
+
 T0 = time.time()
 
 
@@ -509,6 +524,7 @@ def main():
     # kernel really moves between L2 and the fabric (Infinity Cache hits included)
     mean_launch_s = float(np.mean(per_mode_ms)) * 1e-3
     fabric_gbps = traffic / mean_launch_s / 1e9 if traffic is not None else None
+    ceiling = gather_ceiling()
     value = N * st.nnz / (ms_step * 1e-3)
     if cpu is not None:
         cpu["gpu_over_cpu"] = value / cpu["value"]
@@ -526,6 +542,9 @@ def main():
                      "traffic_source": traffic_src,
                      "traffic_GBps": fabric_gbps,
                      "traffic_frac": fabric_gbps / HBM_PEAK_GBS if fabric_gbps is not None else None,
+                     "l2_miss_ceiling_GBps": ceiling,
+                     "traffic_over_l2_miss_ceiling": (fabric_gbps / ceiling
+                                                      if fabric_gbps is not None and ceiling else None),
                      "kernel": "mttkrp_kernel (fp32)",
                      "bytes_model": "per mode: nnz*(4N+4) + sum_{w!=d} touched_w*R*4 + I_d*R*4"},
         "per_mode": per_mode,
