@@ -42,15 +42,16 @@ def measured_traffic(workload, lib_path):
     return None, None
 
 
-def gather_ceiling():
-    """The GPU's measured rate for random 128-byte row gathers that miss the
-    L2 but hit the Infinity Cache (the fastest an L2 miss returns), from the
-    committed summary profiles/gather_ceiling_mi355x.md (the `ceiling_GBps:`
-    line), or None."""
+def gather_ceiling(key="ceiling_GBps"):
+    """A measured row-gather rate of the GPU from the committed summary
+    profiles/gather_ceiling_mi355x.md, or None.  `ceiling_GBps`: random
+    128-byte rows that miss the L2 but hit the Infinity Cache (the fastest an
+    L2 miss returns); `row_request_ceiling_GBps`: random rows that hit the L2
+    (the fastest the CUs issue row loads of the kernel's shape)."""
     path = os.path.join(PROFILES, "gather_ceiling_mi355x.md")
     try:
         for line in open(path):
-            if line.startswith("ceiling_GBps:"):
+            if line.startswith(key + ":"):
                 return float(line.split(":", 1)[1])
     except OSError:
         pass
@@ -525,6 +526,10 @@ def main():
     mean_launch_s = float(np.mean(per_mode_ms)) * 1e-3
     fabric_gbps = traffic / mean_launch_s / 1e9 if traffic is not None else None
     ceiling = gather_ceiling()
+    issue_ceiling = gather_ceiling("row_request_ceiling_GBps")
+    # factor rows the kernel asks for per launch (every gathered row, also those the
+    # L1 or the LDS hot-row cache then serve), over the mean launch time
+    rows_gbps = st.nnz * (N - 1) * R * 4 / mean_launch_s / 1e9
     value = N * st.nnz / (ms_step * 1e-3)
     if cpu is not None:
         cpu["gpu_over_cpu"] = value / cpu["value"]
@@ -545,6 +550,9 @@ def main():
                      "l2_miss_ceiling_GBps": ceiling,
                      "traffic_over_l2_miss_ceiling": (fabric_gbps / ceiling
                                                       if fabric_gbps is not None and ceiling else None),
+                     "rows_requested_GBps": rows_gbps,
+                     "row_request_ceiling_GBps": issue_ceiling,
+                     "rows_requested_over_ceiling": rows_gbps / issue_ceiling if issue_ceiling else None,
                      "kernel": "mttkrp_kernel (fp32)",
                      "bytes_model": "per mode: nnz*(4N+4) + sum_{w!=d} touched_w*R*4 + I_d*R*4"},
         "per_mode": per_mode,
