@@ -19,8 +19,10 @@
 //    the product is the row).  Per-slab fp32 partials are summed in fp64 by
 //    gram_reduce, in slab order (deterministic).
 //  * als_small: one block, fp64: V, V^{-1} (Gauss-Jordan), P, lambda,
-//    the new G_d, W (fp32) and, after the last mode, the fit.
-//  * als_solve: A_d = M W, 64 rows per block staged through LDS with W.
+//    the new G_d, W and, after the last mode, the fit.
+//  * als_solve: A_d = M W, a persistent grid over tiles of rows (256 at
+//    R <= 32) staged through LDS beside W; the next tile's rows are loaded
+//    into registers while the current one is computed.
 //  * tensor_norm2: ||X||^2 over the mode-0 layout, exact duplicates (adjacent
 //    there) summed before squaring.
 #include <hip/hip_runtime.h>
@@ -374,9 +376,13 @@ __device__ __forceinline__ void solve_tile(const Acc* sW, int RW, const float* s
     }
 }
 
+// Persistent: block b takes tiles b, b + grid, ... of RB rows.  W goes to LDS
+// once per block.  With R % 4 == 0 each thread holds its part of the next
+// tile's rows of M (up to 8 float4) in registers, loaded before the current
+// tile is computed, so the loads overlap the arithmetic and the stores.
 template <int RPT>
 __global__ void __launch_bounds__(256) als_solve(const float* M, const double* W, const int* wide_flag, float* A,
-                                                 int64_t rows, int R, int RB)
+                                                 int64_t rows, int R, int RB, int64_t ntiles)
 {
     extern __shared__ __align__(16) double s_solve[];
     const int C8 = (R + 7) / 8;                 // column groups of 8
@@ -392,38 +398,47 @@ __global__ void __launch_bounds__(256) als_solve(const float* M, const double* W
         if (wide) sW[e] = w;
         else sWf[e] = (float)w;
     }
-    const int64_t r0 = (int64_t)blockIdx.x * RB;
-    const int nr = (int)std::min<int64_t>(RB, rows - r0);
-    if ((R & 3) == 0) {
-        // 8 loads per thread in flight before their LDS stores
-        const float4* M4 = reinterpret_cast<const float4*>(M + r0 * R);
-        const int n4 = nr * R / 4;
-        for (int base = 0; base < n4; base += 8 * 256) {
-            float4 v[8];
+    const bool vec = (R & 3) == 0;
+    const float4* M4 = reinterpret_cast<const float4*>(M);
+    float4 v[8];   // RB * R / 4 <= 8 * 256 (launch_als_solve)
+    auto fetch = [&](int64_t t) {
+        const int64_t r0 = t * RB;
+        const int n4 = t < ntiles ? (int)(std::min<int64_t>(RB, rows - r0) * R / 4) : 0;
+        const float4* src = M4 + (t < ntiles ? r0 * (R / 4) : 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = u * 256 + tid;
+            v[u] = e < n4 ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (vec) fetch(blockIdx.x);
+    const int g = tid / C8, c8 = tid % C8;
+    const int i0 = RPT * g;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t r0 = t * RB;
+        const int nr = (int)std::min<int64_t>(RB, rows - r0);
+        __syncthreads();   // W staged; the previous tile's reads of sM done
+        if (vec) {
+            const int n4 = nr * R / 4;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int e = base + u * 256 + tid;
-                v[u] = e < n4 ? M4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = base + u * 256 + tid;
+                const int e = u * 256 + tid;
                 if (e < n4) {
                     const int i = (4 * e) / R, k = (4 * e) % R;
                     float* d = &sM[i * (R + 1) + k];
                     d[0] = v[u].x; d[1] = v[u].y; d[2] = v[u].z; d[3] = v[u].w;
                 }
             }
+        } else {
+            for (int e = tid; e < nr * R; e += 256) sM[(e / R) * (R + 1) + e % R] = M[r0 * R + e];
         }
-    } else {
-        for (int e = tid; e < nr * R; e += 256) sM[(e / R) * (R + 1) + e % R] = M[r0 * R + e];
+        __syncthreads();
+        if (vec) fetch(t + gridDim.x);
+        if (i0 < nr) {
+            if (wide) solve_tile<RPT, double>(sW, RW, sM, R, i0, nr, c8, A, r0);
+            else solve_tile<RPT, float>(sWf, RW, sM, R, i0, nr, c8, A, r0);
+        }
     }
-    __syncthreads();
-    const int g = tid / C8, c8 = tid % C8;
-    const int i0 = RPT * g;
-    if (i0 >= nr) return;
-    if (wide) solve_tile<RPT, double>(sW, RW, sM, R, i0, nr, c8, A, r0);
-    else solve_tile<RPT, float>(sWf, RW, sM, R, i0, nr, c8, A, r0);
 }
 
 // ||X||^2 over a layout whose exact duplicates are adjacent (mode 0's).
@@ -554,9 +569,19 @@ hipError_t launch_als_solve(const float* M, const double* W, const int* wide, fl
     const int rpt = R > 64 ? 2 : 4;
     const int RB = rpt * (256 / C8);    // rows per block
     const size_t lds = (size_t)R * 8 * C8 * sizeof(double) + (size_t)RB * (R + 1) * sizeof(float);
-    const dim3 grid((unsigned)((rows + RB - 1) / RB));
-    if (rpt == 4) hipLaunchKernelGGL(als_solve<4>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB);
-    else hipLaunchKernelGGL(als_solve<2>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB);
+    if ((int64_t)RB * R > 8 * 256 * 4) return hipErrorInvalidValue;   // the kernel holds 8 float4 per thread
+    const int64_t ntiles = (rows + RB - 1) / RB;
+    // persistent grid: as many blocks as fit on the GPU at once
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = rpt == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, als_solve<4>, 256, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, als_solve<2>, 256, lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)std::max(per_cu, 1) * cus)));
+    if (rpt == 4) hipLaunchKernelGGL(als_solve<4>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB, ntiles);
+    else hipLaunchKernelGGL(als_solve<2>, grid, dim3(256), lds, st, M, W, wide, A, rows, R, RB, ntiles);
     return hipGetLastError();
 }
 

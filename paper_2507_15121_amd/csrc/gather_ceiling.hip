@@ -13,6 +13,13 @@
 // a multiplicative bijection).  Prints one line per lane layout: lanes per
 // row segment LPR = 8 (whole rows per group, as the kernel), 4 and 2 (half
 // and quarter rows, twice and four times as many rows per instruction).
+//
+//   gather_ceiling stream BYTES
+//
+// Sequential streaming rates over arrays of BYTES bytes (16-byte loads and
+// stores, 8 per thread in flight, grid-stride): read only, write only, and
+// copy (read + write), at 2, 4, 8 and 16 blocks of 256 threads per CU: what
+// a streaming kernel of this GPU reaches against the 8 TB/s HBM peak.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +27,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <string>
 #include <vector>
 
 #define CHECK(x)                                                                           \
@@ -100,10 +108,102 @@ float time_ms(const float4* table, const int* idx, long nidx, float* out, int gr
     return ms / reps;
 }
 
+// Streaming kernels over n 16-byte elements, U in flight per thread.
+template <int U>
+__global__ __launch_bounds__(256) void stream_copy(const float4* __restrict__ a, float4* __restrict__ b, long n)
+{
+    const long stride = (long)gridDim.x * 256 * U;
+    for (long base = (long)blockIdx.x * 256 * U + threadIdx.x; base < n; base += stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long i = base + (long)u * 256;
+            v[u] = i < n ? a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long i = base + (long)u * 256;
+            if (i < n) b[i] = v[u];
+        }
+    }
+}
+
+template <int U>
+__global__ __launch_bounds__(256) void stream_read(const float4* __restrict__ a, float* out, long n)
+{
+    const long stride = (long)gridDim.x * 256 * U;
+    float s = 0.f;
+    for (long base = (long)blockIdx.x * 256 * U + threadIdx.x; base < n; base += stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long i = base + (long)u * 256;
+            v[u] = i < n ? a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    out[(long)blockIdx.x * 256 + threadIdx.x] = s;   // one float per thread keeps the loads
+}
+
+__global__ __launch_bounds__(256) void stream_write(float4* b, long n)
+{
+    const long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) b[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+int stream_main(long bytes)
+{
+    const long n = bytes / 16;
+    if (n < 1) {
+        std::fprintf(stderr, "BYTES must be at least 16\n");
+        return 2;
+    }
+    int cus = 0;
+    CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    float4 *a, *b;
+    float* out;
+    CHECK(hipMalloc(&a, n * 16));
+    CHECK(hipMalloc(&b, n * 16));
+    CHECK(hipMalloc(&out, (long)cus * 16 * 256 * sizeof(float)));
+    CHECK(hipMemset(a, 0, n * 16));
+    CHECK(hipMemset(b, 0, n * 16));
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    auto timed = [&](auto launch) {
+        launch();
+        CHECK(hipDeviceSynchronize());
+        CHECK(hipEventRecord(e0, 0));
+        for (int k = 0; k < 5; ++k) launch();
+        CHECK(hipEventRecord(e1, 0));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        CHECK(hipGetLastError());
+        return ms / 5;
+    };
+    for (int bpc : {2, 4, 8, 16}) {
+        const int grid = cus * bpc;
+        const float r = timed([&] { hipLaunchKernelGGL(stream_read<8>, dim3(grid), dim3(256), 0, 0, a, out, n); });
+        const float w = timed([&] { hipLaunchKernelGGL(stream_write, dim3(grid), dim3(256), 0, 0, b, n); });
+        const float c = timed([&] { hipLaunchKernelGGL(stream_copy<8>, dim3(grid), dim3(256), 0, 0, a, b, n); });
+        std::printf("stream %.3g GB, %d blocks/CU: read %.3f ms %.0f GB/s, write %.3f ms %.0f GB/s, "
+                    "copy %.3f ms %.0f GB/s (read + write bytes)\n",
+                    n * 16e-9, bpc, r, n * 16 / (r * 1e-3) / 1e9, w, n * 16 / (w * 1e-3) / 1e9, c,
+                    2.0 * n * 16 / (c * 1e-3) / 1e9);
+    }
+    CHECK(hipFree(a));
+    CHECK(hipFree(b));
+    CHECK(hipFree(out));
+    return 0;
+}
+
 int main(int argc, char** argv)
 {
+    if (argc == 3 && std::string(argv[1]) == "stream") return stream_main(std::atol(argv[2]));
     if (argc < 4) {
-        std::fprintf(stderr, "usage: %s ROWS GATHERS ZIPF_S [BLOCKS_PER_CU]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s ROWS GATHERS ZIPF_S [BLOCKS_PER_CU] | %s stream BYTES\n", argv[0], argv[0]);
         return 2;
     }
     const long rows = std::atol(argv[1]);
