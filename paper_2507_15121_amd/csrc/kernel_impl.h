@@ -893,7 +893,8 @@ KernelFn pick_grad_loss(int nin, int lpr, bool scalar, bool buf);
 // The instance each picker returns: lpr counts 16-byte lanes per row (the
 // vector path), scalar selects the column-tile path.  bfloat16 rows of up to
 // 64 bytes (rank <= 32) use 8 bytes per lane, so a wave still covers 8 rows
-// per gather at rank 32 (16-byte lanes would make 16 narrow groups).
+// per gather at rank 32 (16-byte lanes would make 16 narrow groups), except
+// 64-byte rows with three or more gathered factors (below).
 #ifndef AMPED_BF16_NARROW
 #define AMPED_BF16_NARROW 1
 #endif
@@ -906,7 +907,11 @@ KernelFn pick_vec(int lpr)
         return nullptr;
     } else {
         if constexpr (narrow) {
-            if (lpr <= 4) {
+            // with three or more gathered factors, 64-byte rows take 16-byte
+            // lanes again (16 rows per gather instruction): the order-4
+            // tensors measured faster so, in every mode, the order-3 ones
+            // slower
+            if (lpr == 2 || (lpr == 4 && NIN <= 2)) {
                 switch (lpr) {
                 case 2: return mttkrp_kernel<NIN, 4, 4, T, KIND, BUF>;
                 case 4: return mttkrp_kernel<NIN, 8, 4, T, KIND, BUF>;
