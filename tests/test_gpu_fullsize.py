@@ -195,3 +195,69 @@ def test_bf16_factor_above_4GiB_narrow_lanes():
         assert e <= 1e-5
         assert not torch.isnan(out).any().item()
     T.close()
+
+
+def test_index_space_at_the_int32_limit():
+    """Mode 0 spans the largest index space the ABI accepts (2^31 - 1 rows).
+    At rank 8 its factor and its output are 68.7 GB each, and rows near the top of
+    the index space sit 68 GB into them.  Nearly all 2^31 output rows are
+    untouched, which gives the init kernel about a million gap ranges.  Checked:
+    - every output row is written (NaN prefill);
+    - exactly the touched rows are nonzero;
+    - sampled rows match the oracle on the factor rows they use: the first and
+      last indices, rows from the dense top 5M of the index space, and random ones."""
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 200e9:
+        pytest.skip("needs about 160 GB of free device memory")
+    I0 = 2**31 - 1
+    dims = (I0, 3000, 2000)
+    R = 8
+    rng = np.random.default_rng(31)
+    n = 200_000
+    i0 = np.concatenate([[0, 1, I0 - 2, I0 - 1], rng.integers(I0 - 5_000_000, I0, 100_000),
+                         rng.integers(0, I0, n - 100_004)])
+    idx = np.stack([i0, rng.integers(0, dims[1], n), rng.integers(0, dims[2], n)]).astype(np.int32)
+    val = rng.random(n).astype(np.float32) + 0.5
+    log("int32-limit index space: building layouts")
+    T = api.Tensor(idx, val, dims)
+    dfac = [torch.empty((d, R), device="cuda").uniform_(-1, 1) for d in dims]
+    block = 1 << 28
+    for d in range(3):
+        out = torch.full((dims[d], R), float("nan"), device="cuda")
+        api.mttkrp(T, d, [None if w == d else f for w, f in enumerate(dfac)], out=out)
+        torch.cuda.synchronize()
+        nan_rows = nonzero_rows = 0
+        for a in range(0, dims[d], block):
+            part = out[a:a + block]
+            nan_rows += int(torch.isnan(part).any(dim=1).sum().item())
+            nonzero_rows += int((part != 0).any(dim=1).sum().item())
+        touched = np.unique(idx[d])
+        log("int32-limit mode %d: %d rows, %d touched, %d nonzero rows, %d NaN rows" %
+            (d, dims[d], touched.size, nonzero_rows, nan_rows))
+        assert nan_rows == 0
+        assert nonzero_rows == touched.size
+        pick = rng.choice(touched, size=min(300, touched.size), replace=False)
+        rows = np.unique(np.concatenate([pick, touched[:2], touched[-2:]]))
+        got = out[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy()
+        del out
+        m = np.isin(idx[d], rows)
+        sub = idx[:, m].astype(np.int64)
+        fs, cdims = [], []
+        for w in range(3):
+            if w == d:
+                sub[w] = np.searchsorted(rows, sub[w])
+                fs.append(np.zeros((rows.size, R)))
+                cdims.append(rows.size)
+            else:
+                used = np.unique(sub[w])
+                fs.append(dfac[w][torch.from_numpy(used).cuda()].double().cpu().numpy())
+                sub[w] = np.searchsorted(used, sub[w])
+                cdims.append(used.size)
+        e = oracle.rel_fro(got, oracle.mttkrp(sub.astype(np.int32), val[m], cdims, fs, d))
+        log("int32-limit mode %d: sampled rel %.2e (rows %d..%d)" % (d, e, rows[0], rows[-1]))
+        assert e <= 1e-5
+        torch.cuda.empty_cache()
+    T.close()
+    del dfac
+    torch.cuda.empty_cache()
