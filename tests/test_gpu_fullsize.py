@@ -261,3 +261,76 @@ def test_index_space_at_the_int32_limit():
     T.close()
     del dfac
     torch.cuda.empty_cache()
+
+
+def test_largest_nonzero_count_in_chunks_of_one():
+    """2^31 - 1 nonzeros, the most the ABI accepts, in chunks of one nonzero:
+    2^31 - 1 work-queue chunks, the largest count the queue counters meet.
+    Mode 0 has 2^31 - 1 rows with one nonzero each, so each chunk stores one
+    whole row.  Only mode 0 is computed here.  In modes 1 and 2 every row has
+    thousands of one-nonzero chunks, all added atomically into the same row.
+    The inputs are integers, so every output value is exact.  Checked:
+    - no row is left unwritten (NaN prefill);
+    - the column sums of the whole output equal int64 sums of the per-nonzero
+      terms;
+    - sampled rows equal the oracle bit for bit."""
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 240e9:
+        pytest.skip("needs about 200 GB of free device memory")
+    nnz = 2**31 - 1
+    dims = (nnz, 1 << 19, 1 << 14)
+    R = 8
+    idx = np.empty((3, nnz), np.int32)
+    val = np.empty(nnz, np.float32)
+    step = 1 << 27
+    for a in range(0, nnz, step):
+        k = np.arange(a, min(a + step, nnz), dtype=np.int64)
+        idx[0, a:a + k.size] = k
+        idx[1, a:a + k.size] = (k * 40503 + k // 977) % dims[1]
+        idx[2, a:a + k.size] = (k * 69069 + 12345) % dims[2]
+        val[a:a + k.size] = (k % 3 + 1).astype(np.float32)
+    rng = np.random.default_rng(7)
+    fac = [None] + [rng.integers(-2, 3, (d, R)).astype(np.float32) for d in dims[1:]]
+    log("2^31 - 1 nonzeros, chunks of one: building layouts")
+    T = api.Tensor(idx, val, dims, chunk_nnz=1)
+    assert T.n_chunks == nnz
+    dfac = [None] + [torch.from_numpy(f).cuda() for f in fac[1:]]
+    out = torch.full((nnz, R), float("nan"), device="cuda")
+    api.mttkrp(T, 0, dfac, out=out)
+    torch.cuda.synchronize()
+    log("mode 0 done; checking")
+    # column sums: output (exact integers in fp32, summed in fp64) against int64 terms
+    got_sum = torch.zeros(R, dtype=torch.float64, device="cuda")
+    nan_rows = 0
+    for a in range(0, nnz, step):
+        part = out[a:a + step]
+        nan_rows += int(torch.isnan(part).any(dim=1).sum().item())
+        got_sum += part.double().sum(dim=0)
+    assert nan_rows == 0
+    f1 = dfac[1].long()
+    f2 = dfac[2].long()
+    ref_sum = torch.zeros(R, dtype=torch.int64, device="cuda")
+    for a in range(0, nnz, 1 << 25):
+        b = min(a + (1 << 25), nnz)
+        i1 = torch.from_numpy(idx[1, a:b]).cuda().long()
+        i2 = torch.from_numpy(idx[2, a:b]).cuda().long()
+        v = torch.from_numpy(val[a:b]).cuda().long()
+        ref_sum += (v[:, None] * f1[i1] * f2[i2]).sum(dim=0)
+    log("column sums %s (int64 terms %s)" % (got_sum.cpu().numpy(), ref_sum.cpu().numpy()))
+    assert torch.equal(got_sum, ref_sum.double())
+    rows = np.unique(np.concatenate([[0, 1, nnz - 2, nnz - 1], rng.integers(0, nnz, 300)]))
+    got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del out
+    sub = idx[:, rows].astype(np.int64)
+    fs, cdims = [np.zeros((rows.size, R))], [rows.size]
+    sub[0] = np.arange(rows.size)
+    for w in (1, 2):
+        used = np.unique(sub[w])
+        fs.append(fac[w][used].astype(np.float64))
+        sub[w] = np.searchsorted(used, sub[w])
+        cdims.append(used.size)
+    ref = oracle.mttkrp(sub.astype(np.int32), val[rows], cdims, fs, 0).astype(np.float32)
+    np.testing.assert_array_equal(got, ref)
+    T.close()
+    torch.cuda.empty_cache()
