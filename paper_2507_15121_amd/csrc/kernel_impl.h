@@ -10,8 +10,9 @@
 //    Sec. 4.2: each wave takes the next chunk from a device atomic counter
 //    until none is left, so skewed slices spread over all CUs.
 //  * Inside a chunk the wave is G groups of LPR lanes.  Each lane holds RPL
-//    consecutive columns of a factor row (16 bytes; 8 for bf16 rows of up to
-//    64 bytes), so a group loads a whole row with one coalesced access.  Group g walks its own contiguous run of
+//    consecutive columns of a factor row (16 bytes; 8 for bf16 rows of 32
+//    bytes, and of 64 bytes when at most two factors are gathered), so a group
+//    loads a whole row with one coalesced access.  Group g walks its own contiguous run of
 //    the chunk's nonzeros in order and keeps the running sum of the current
 //    output row in registers (the elementwise computation, EC of Sec. 3,
 //    reduced over consecutive equal output indices instead of one atomic per
