@@ -334,3 +334,45 @@ def test_largest_nonzero_count_in_chunks_of_one():
     np.testing.assert_array_equal(got, ref)
     T.close()
     torch.cuda.empty_cache()
+
+
+def test_bf16_factor_above_4GiB_order_4_wide_lanes():
+    """bf16 factors at rank 32 with three gathered factors (order 4): 64-byte rows
+    gathered with 16-byte lanes.  A 72M-row factor is 4.6 GB, past 32-bit buffer
+    offsets, so modes 1-3 gather it with 64-bit addresses.  The oracle sees the
+    same bf16 values (exactly widened) on the rows the sampled outputs use."""
+    dims = (72_000_000, 1000, 500, 300)
+    R = 32
+    st = synth.tensor(dims, 2_000_000, "zipf", 1.1, 0.0, seed=14)
+    T = api.Tensor(st.idx, st.val, dims)
+    rng = np.random.default_rng(14)
+    dbf = []
+    for d in dims:
+        f = torch.empty((d, R), device="cuda").uniform_(-1, 1)
+        dbf.append(f.to(torch.bfloat16))
+        del f
+    for d in (1, 2, 3):
+        out = torch.full((dims[d], R), float("nan"), device="cuda")
+        api.mttkrp_bf16(T, d, [None if w == d else f for w, f in enumerate(dbf)], out=out)
+        torch.cuda.synchronize()
+        rows, _, _ = _sample_rows(st, d, rng, 200)
+        got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+        m = np.isin(st.idx[d], rows)
+        sub = st.idx[:, m].astype(np.int64)
+        fs, cdims = [], []
+        for w in range(4):
+            if w == d:
+                sub[w] = np.searchsorted(rows, sub[w])
+                fs.append(np.zeros((rows.size, R)))
+                cdims.append(rows.size)
+            else:
+                used = np.unique(sub[w])
+                fs.append(dbf[w][torch.from_numpy(used).cuda()].float().double().cpu().numpy())
+                sub[w] = np.searchsorted(used, sub[w])
+                cdims.append(used.size)
+        ref = oracle.mttkrp(sub.astype(np.int32), st.val[m], cdims, fs, d)
+        e = oracle.rel_fro(got, ref)
+        log("4.6 GB bf16 factor, order 4, mode %d: sampled rel %.2e" % (d, e))
+        assert e <= 1e-5
+        assert not torch.isnan(out).any().item()
+    T.close()
